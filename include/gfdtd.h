@@ -1,0 +1,292 @@
+/*
+ * gfdtd.h -- C-ABI of the MI355X generalized-FDTD library.
+ *
+ * The library time-steps the generalized FDTD scheme of Deck-Leger,
+ * Bahrami, Li and Caloz (arXiv 2304.06586) for electromagnetic scattering
+ * in 1D moving structures: the extended Yee cell of Section 3 (Fig. 2),
+ * whose tangential unknowns are the auxiliary fields
+ *     E* = E + v x B,   H* = H - v x D          (eq. (2)),
+ * updated by the leapfrog equations (10a)-(10d) with the dynamic
+ * (velocity) terms of Table 1.  Every step re-samples the moving material
+ * profile eps(z - v t), mu(z - v t) (eq. (5)), so the moving-boundary
+ * conditions (1a)-(1d) hold implicitly at every cell the moving structure
+ * crosses.  Each step also injects a source, absorbs at the grid ends and
+ * records probes.  All of that runs in HIP kernels on the GPU.
+ *
+ * Units: c = eps0 = mu0 = 1, cell size dz = 1, time step S = dt/dz
+ * (Courant number, below eq. (10)), beta = v/c.
+ *
+ * Grid: nz E nodes k = 0..nz-1 (D_x, E*_x at times n+1/2) and nz-1 H nodes
+ * j = 0..nz-2 at positions j+1/2 (B_y, H*_y at integer times n).
+ *
+ * Conventions
+ *  - Every function returns a gfdtd_status; nothing throws across the ABI.
+ *    gfdtd_last_error() returns a message for the calling thread's last
+ *    failure.
+ *  - Host inputs are caller-owned and only read during the call.
+ *  - Device memory is caller-owned: the caller allocates a workspace of
+ *    at least the size the *_bytes queries report and passes its device
+ *    pointer and size.  The library carves it and never calls hipMalloc.
+ *    The workspace must stay allocated while a batch or server that uses
+ *    it exists.
+ *  - Streams are passed as void* (a hipStream_t); work is ordered on that
+ *    stream.
+ *  - Structs start with struct_size = sizeof(struct) for ABI evolution.
+ *  - Different batches/servers are independent; one batch or server must
+ *    not be used from two threads at once.
+ */
+#ifndef GFDTD_H
+#define GFDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef enum gfdtd_status {
+    GFDTD_OK = 0,
+    GFDTD_E_INVALID = 1,     /* bad argument or problem description        */
+    GFDTD_E_UNSTABLE = 2,    /* pre-flight: amplification factor above 1   */
+    GFDTD_E_NOMEM = 3,       /* workspace / server pool too small          */
+    GFDTD_E_DEVICE = 4,      /* a HIP call failed                          */
+    GFDTD_E_NOT_READY = 5,   /* server: request still queued or running    */
+    GFDTD_E_BLOWUP = 6,      /* a probe recorded NaN or Inf                */
+    GFDTD_E_UNSUPPORTED = 7  /* option not implemented                     */
+} gfdtd_status;
+
+/* Message naming a status; static storage. */
+const char *gfdtd_status_str(gfdtd_status s);
+/* Message describing the calling thread's last failure ("" if none). */
+const char *gfdtd_last_error(void);
+
+/* ----------------------------------------------------------- the problem */
+#define GFDTD_MODULATION 0   /* moving perturbation: eps(z-vt), mu(z-vt)
+                                stay isotropic (Section 2)                  */
+#define GFDTD_MATTER 1       /* moving matter: bianisotropic in the lab
+                                frame (footnote to eq. (5)), here in the
+                                solved form E* = g (mu' D - beta Bbar),
+                                H* = g (eps' B - beta Dbar),
+                                g = (1-beta^2)/(eps' mu' - beta^2)          */
+
+#define GFDTD_F32 0          /* FP32 fields and stencil arithmetic; moving-
+                                boundary shifts, coefficients before
+                                rounding, source samples, probes and DFT in
+                                FP64                                        */
+#define GFDTD_F64 1          /* everything in FP64                          */
+
+#define GFDTD_ABC_MUR1 0     /* first-order Mur on D at both end nodes      */
+#define GFDTD_ABC_PEC 1      /* D = 0 at both end nodes                     */
+
+#define GFDTD_FLAG_RECORD_TRACE 1u   /* copy probe time traces on collect  */
+#define GFDTD_FLAG_ALLOW_UNSTABLE 2u /* skip the pre-flight rejection      */
+#define GFDTD_FLAG_KEEP_FIELDS 4u    /* server: keep the final fields until
+                                        the request is polled              */
+
+#define GFDTD_MAX_PROBES 64
+
+/*
+ * One scattering solve.
+ *  eps_rest[i]  rest permittivity eps' of the cell centred on E node i
+ *               (covering z in [i-1/2, i+1/2) at t = 0), i = 0..nz-1;
+ *  mu_rest[i]   rest permeability mu' of the cell centred on H node i
+ *               (covering [i, i+1)); entry nz-1 is read only by the
+ *               moving-matter end treatment and may be any positive value.
+ *  The profile moves rigidly at beta (eq. (5): eps(z - v t)), in whole
+ *  cells: at time tau*S it has moved by m = rint(beta*S*tau) cells and a
+ *  node at lattice index x reads rest cell clamp(x - m).  E nodes read
+ *  at tau = n+1/2, H nodes at tau = n.  For moving matter both eps' and
+ *  mu' are read at the node's own lattice index.
+ *  Source: soft source added to D at src_cell after (10b) of step n,
+ *    src_amp * sin(src_omega (t - src_t0) + src_phase)
+ *            * exp(-((t - src_t0)/src_tau)^2),  t = n S,
+ *  for t <= src_t_off (the modulated Gaussian of App. B.1).
+ *  Probes: physical E = E* + beta Bbar (inverse of eq. (2), Bbar the
+ *  Table 1 average of (10c)) at probe_cells, at t = (n+1/2) S, n = 1..steps;
+ *  DFT X(w) = sum_n E_n S exp(+i w t_n) at the nfreq angular frequencies.
+ *  Values off the grid are the edge values.
+ */
+typedef struct gfdtd_problem {
+    uint32_t struct_size;
+    int32_t kind;                /* GFDTD_MODULATION / GFDTD_MATTER        */
+    int32_t precision;           /* GFDTD_F32 / GFDTD_F64                  */
+    int32_t abc;                 /* GFDTD_ABC_*                            */
+    uint32_t flags;              /* GFDTD_FLAG_*                           */
+    int32_t nprobe;              /* 0..GFDTD_MAX_PROBES                    */
+    int32_t nfreq;               /* >= 0                                   */
+    int32_t reserved0;
+    int64_t nz;                  /* E nodes, >= 8                          */
+    double courant;              /* S = dt/dz, > 0                         */
+    double beta;                 /* v/c, |beta| < 1                        */
+    const double *eps_rest;      /* host, nz, > 0 and finite               */
+    const double *mu_rest;       /* host, nz, > 0 and finite               */
+    int64_t src_cell;            /* 1..nz-2                                */
+    double src_amp, src_omega, src_t0, src_tau, src_phase, src_t_off;
+    const int64_t *probe_cells;  /* host, nprobe, each in 0..nz-1          */
+    const double *omegas;        /* host, nfreq                            */
+} gfdtd_problem;
+
+/*
+ * Results of one solve, in caller-allocated host buffers (any pointer may
+ * be NULL to skip that output).  Sizes from gfdtd_result_sizes().
+ *  trace    nprobe*steps doubles, probe q at row q (needs
+ *           GFDTD_FLAG_RECORD_TRACE);
+ *  dft_re/im nprobe*nfreq doubles, probe q at row q;
+ *  final_d  nz doubles: D^{steps+1/2} (converted from the run precision);
+ *  final_b  nz doubles: B^{steps} at H nodes 0..nz-2, last entry 0.
+ */
+typedef struct gfdtd_result {
+    uint32_t struct_size;
+    int32_t run_status;          /* GFDTD_OK or GFDTD_E_BLOWUP             */
+    int64_t steps_done;
+    double *trace;
+    double *dft_re;
+    double *dft_im;
+    double *final_d;
+    double *final_b;
+} gfdtd_result;
+
+/*
+ * Validate a problem and run the stability pre-flight: the von Neumann
+ * amplification matrix of one step (Section 5, App. A) is evaluated for
+ * every distinct medium of the rest profile, theta in (0, pi]; the larger
+ * of the two roots (co- and contra-moving, Section 5) must not exceed 1.
+ * Writes the largest modulus to *max_growth (may be NULL).
+ * Returns GFDTD_E_INVALID for a malformed problem, GFDTD_E_UNSTABLE when
+ * the growth exceeds 1 + 1e-9 and GFDTD_FLAG_ALLOW_UNSTABLE is not set.
+ * Host only; does not touch the GPU.
+ */
+gfdtd_status gfdtd_check(const gfdtd_problem *p, double *max_growth);
+
+/* Lengths (in doubles) of the trace and DFT outputs of one solve. */
+gfdtd_status gfdtd_result_sizes(const gfdtd_problem *p, int64_t steps,
+                                size_t *trace_len, size_t *dft_len);
+
+/* Device workspace needed by gfdtd_solve (one problem) and by a batch. */
+gfdtd_status gfdtd_workspace_bytes(const gfdtd_problem *p, int64_t steps,
+                                   size_t *bytes);
+gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
+                                         const int64_t *steps, int32_t count,
+                                         size_t *bytes);
+
+/* ------------------------------------------------------------- execution */
+#define GFDTD_VARIANT_AUTO 0
+#define GFDTD_VARIANT_STEP 1     /* one launch per time step               */
+#define GFDTD_VARIANT_TILED 2    /* register tiles, several steps a launch */
+
+/*
+ * Execution options (NULL = automatic).  cells_per_lane in {4, 8, 16}
+ * (0 = auto), block_steps = temporal block depth, steps per launch
+ * (0 = auto; 1 for GFDTD_VARIANT_STEP), use_graph: -1 auto, 0 plain
+ * launches, 1 capture the launch sequence in a hipGraph.
+ * The result does not depend on these options (bit for bit).
+ */
+typedef struct gfdtd_exec {
+    uint32_t struct_size;
+    int32_t variant;
+    int32_t cells_per_lane;
+    int32_t block_steps;
+    int32_t use_graph;
+    int32_t reserved0;
+} gfdtd_exec;
+
+/*
+ * Plain single solve: validate, pre-flight, upload, step, collect.
+ * Synchronous: on return the results are in *out.  ws/ws_bytes is device
+ * memory of at least gfdtd_workspace_bytes().
+ */
+gfdtd_status gfdtd_solve(const gfdtd_problem *p, int64_t steps, void *ws,
+                         size_t ws_bytes, void *stream, gfdtd_result *out);
+
+/*
+ * Many independent solves in one pass: the runs are packed into one run
+ * table and every launch advances all live runs by one temporal block.
+ * outs[i] receives run i's results; its run_status reports a blow-up of
+ * that run alone.  Synchronous.
+ */
+gfdtd_status gfdtd_solve_batch(const gfdtd_problem *probs, const int64_t *steps,
+                               int32_t count, void *ws, size_t ws_bytes,
+                               void *stream, gfdtd_result *outs);
+
+/* Split form of a batch: prepare once, run (possibly many times), collect. */
+typedef struct gfdtd_batch gfdtd_batch;
+
+/*
+ * Validate and pre-flight every problem, carve the workspace, upload rest
+ * profiles, probes and frequencies, and build the launch plan (and the
+ * hipGraph if requested).  Enqueues uploads on `stream`.
+ */
+gfdtd_status gfdtd_batch_prepare(const gfdtd_problem *probs,
+                                 const int64_t *steps, int32_t count,
+                                 const gfdtd_exec *exec, void *ws,
+                                 size_t ws_bytes, void *stream,
+                                 gfdtd_batch **out);
+/*
+ * Enqueue one complete pass on the stream: zero the fields, time-step
+ * every run to its step count, then form the probe DFTs.  Device work
+ * only; returns without waiting.  Each pass recomputes from zero fields.
+ */
+gfdtd_status gfdtd_batch_run(gfdtd_batch *b);
+/* Wait for the stream, then copy run i's results to outs[i]. */
+gfdtd_status gfdtd_batch_collect(gfdtd_batch *b, gfdtd_result *outs);
+
+typedef struct gfdtd_stats {
+    uint32_t struct_size;
+    int32_t cells_per_lane;      /* chosen tiling                          */
+    int32_t block_steps;         /* temporal block depth                   */
+    int32_t graph;               /* 1 if passes replay a hipGraph          */
+    int64_t launches;            /* stepping launches per pass             */
+    int64_t tiles;               /* wave tiles summed over launches        */
+    double cell_updates;         /* sum over runs of nz * steps            */
+    double step_ms;              /* device time of the last pass's stepping
+                                    launches (HIP events on the stream)    */
+    double pass_ms;              /* device time of the whole last pass     */
+} gfdtd_stats;
+
+gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
+void gfdtd_batch_destroy(gfdtd_batch *b);
+
+/* --------------------------------------------------------------- serving */
+/*
+ * Continuous-batching server.  Requests are admitted while their device
+ * state fits in the pool (the HBM budget) and a slot is free; every
+ * progress block advances all admitted runs by block_steps steps in one
+ * launch per precision and kind; finished runs are retired (DFT, copy-out)
+ * between blocks and queued requests admitted in their place.  A result
+ * does not depend on which other requests shared its blocks.
+ */
+typedef struct gfdtd_server_config {
+    uint32_t struct_size;
+    int32_t max_slots;           /* admitted runs at once, >= 1            */
+    int32_t block_steps;         /* steps per progress block (0 = auto)    */
+    int32_t reserved0;
+    void *pool;                  /* device memory for run state            */
+    size_t pool_bytes;           /* the HBM budget                         */
+    void *stream;
+} gfdtd_server_config;
+
+typedef struct gfdtd_server gfdtd_server;
+
+gfdtd_status gfdtd_server_create(const gfdtd_server_config *cfg,
+                                 gfdtd_server **out);
+/* Queue a request.  GFDTD_E_NOMEM only if the request alone can never fit
+ * the pool; GFDTD_E_INVALID / GFDTD_E_UNSTABLE as gfdtd_check. */
+gfdtd_status gfdtd_server_submit(gfdtd_server *s, const gfdtd_problem *p,
+                                 int64_t steps, uint64_t *id);
+/* Run up to max_blocks progress blocks (admit, step, retire).  *live gets
+ * the number of admitted runs afterwards, *queued the waiting ones (either
+ * may be NULL). */
+gfdtd_status gfdtd_server_progress(gfdtd_server *s, int32_t max_blocks,
+                                   int32_t *live, int32_t *queued);
+/* Copy a finished request's results (GFDTD_E_NOT_READY before).  A
+ * request's results can be polled once; its record is then released. */
+gfdtd_status gfdtd_server_poll(gfdtd_server *s, uint64_t id, gfdtd_result *out);
+void gfdtd_server_destroy(gfdtd_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFDTD_H */

@@ -1,0 +1,13 @@
+"""MI355X-native generalized FDTD for electromagnetic scattering in moving
+structures (Deck-Leger, Bahrami, Li, Caloz, arXiv 2304.06586).
+
+The hot path -- leapfrog stepping of the generalized Yee cell with the
+moving-boundary sampling, source, absorbing ends and probes -- runs in HIP
+kernels for gfx950 behind the C-ABI of include/gfdtd.h (libgfdtd.so, built
+in-tree).  This package is its thin Python binding.
+"""
+from .gfdtd import (  # noqa: F401
+    Batch, GfdtdError, Server, gfdtd_batch_workspace_bytes, gfdtd_check,
+    gfdtd_result_sizes, gfdtd_solve, gfdtd_solve_batch, gfdtd_status_str,
+    gfdtd_workspace_bytes, load_library,
+)

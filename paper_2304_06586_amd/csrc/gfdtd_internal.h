@@ -1,0 +1,95 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// the generalized-FDTD library.  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gfdtd {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kWavesPerGroup = 4;    // independent wave tiles per workgroup
+constexpr int64_t kPad = 2048;       // cells of padding before and after
+                                     // every field array (>= 64 * C)
+
+// One run as the stepping kernels see it.  Field arrays are offset so
+// that index 0 is E node / H node 0 and indices [-kPad, nz + kPad) are
+// addressable.  Coefficient arrays hold one entry per rest cell.
+struct RunDesc {
+    int64_t nz;
+    int64_t steps;
+    int64_t start_block;   // global block index at which step 1 runs
+    int64_t nsrc;          // source samples for steps 1..nsrc
+    int64_t src_cell;
+    int64_t own_cells;     // cells each tile of this run stores
+    double S;              // Courant number
+    double beta;
+    double bS;             // beta * S (one rounding; also the shift rate)
+    double hb;             // beta / 2
+    int32_t neg;           // beta < 0: Table 1 column b
+    int32_t hl;            // halo lanes left of the owned lanes
+    int32_t hr;            // halo lanes right of the owned lanes
+    int32_t nprobe;
+    int32_t abc;           // GFDTD_ABC_*
+    int32_t pad0;
+    void *D[2];            // ping-pong D (run precision)
+    void *B[2];            // ping-pong B
+    const void *cE;        // E-node coefficient: 1/eps' or g mu'
+    const void *cH;        // H-node coefficient: 1/mu'  or g eps'
+    const void *gB;        // moving matter: g beta / 2 (else unused)
+    const double *murL;    // left-end Mur coefficient per rest cell
+    const double *murR;    // right-end Mur coefficient per rest cell
+    const double *src;     // source samples, step n at [n-1]
+    const int64_t *probes; // probe cells
+    double *trace;         // nprobe * steps, probe q at row q
+};
+
+struct TileRef {
+    int32_t run;           // index into the RunDesc array of the launch
+    int32_t tile;          // tile index within that run
+};
+
+// Per-run arguments of the set-up kernels.
+struct PrepDesc {
+    int64_t nz;
+    int64_t nsrc;
+    double S, beta;
+    double amp, omega, t0, tau, phase;
+    int32_t kind;
+    int32_t precision;
+    const double *eps;     // rest profile (device copy)
+    const double *mu;
+    void *cE;
+    void *cH;
+    void *gB;
+    double *murL;
+    double *murR;
+    double *src;
+    void *fields[4];       // D0, D1, B0, B1 (offset by kPad)
+    int64_t field_cells;   // nz + 2 kPad
+};
+
+struct DftDesc {
+    int64_t steps;
+    double S;
+    int32_t nprobe;
+    int32_t nfreq;
+    const double *trace;
+    const double *omegas;
+    double *out;           // nprobe * nfreq * 2 (re, im)
+};
+
+// Launchers (kernels.hip).  Each returns hipSuccess or the launch error.
+hipError_t launch_prep(const PrepDesc *dev_descs, int count, int max_cells,
+                       hipStream_t stream);
+hipError_t launch_zero(const PrepDesc *dev_descs, int count,
+                       int64_t max_field_cells, int precision,
+                       hipStream_t stream);
+hipError_t launch_tiles(int precision, int kind, int C, const RunDesc *runs,
+                        const TileRef *tiles, int64_t block, int T,
+                        int ntiles, hipStream_t stream);
+hipError_t launch_dft(const DftDesc *dev_descs, int count, int max_pf,
+                      hipStream_t stream);
+
+}  // namespace gfdtd

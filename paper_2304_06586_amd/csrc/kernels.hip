@@ -1,0 +1,616 @@
+// HIP kernels of the generalized-FDTD library (gfx950 / CDNA4).
+//
+// The hot kernel, k_tiles, advances wave tiles of one or many runs by a
+// temporal block of T time steps.  A tile is one 64-lane wavefront holding
+// 64*C consecutive cells in registers (C cells per lane, D and B for each);
+// neighbouring values move between lanes with wave shuffles, so a tile
+// needs no LDS and no barriers.  Tiles overlap: the per-step dependency
+// cone of eq. (10) with the Table 1 terms reaches 3 cells upwind and 1 cell
+// downwind (column a, v >= 0) or 1 upwind / 2 downwind (column b), so
+// after T steps only the lanes away from the tile edges hold valid
+// values; those "owned" lanes are written back, to the other half of a
+// ping-pong pair.  HBM traffic per cell-update is therefore about
+// 2 * 2 * sizeof(R) / T plus the halo overhead.
+//
+// Per step and cell (all in registers):
+//   E*   = cE D - hb (B_a + B_b)        (10c) with the Table 1 B average
+//   B'   = B - S (E*_{+1} - E*) - bS dB (10a) with the Table 1 dB/dz
+//   H*   = cH B' - hb (D_{+1} + D)      (10d) with the Table 1 D average
+//   D'   = D - S (H* - H*_{-1}) - bS dD (10b) with the Table 1 dD/dz
+// then the source, the end conditions and the probes.  cE, cH are 1/eps',
+// 1/mu' for a moving modulation; for moving matter cE = g mu', cH = g eps'
+// and hb is replaced by the per-cell g beta / 2.
+//
+// The moving profile: at time tau*S the rest profile has moved by
+// m = rint(beta S tau) whole cells (FP64 on every path), so each lane keeps
+// its cells' coefficients in registers and shifts them by one cell, with
+// one shuffle, whenever m changes.
+
+#include <hip/hip_runtime.h>
+
+#include "gfdtd.h"
+#include "gfdtd_internal.h"
+
+namespace gfdtd {
+
+// ------------------------------------------------------------ wave helpers
+
+template <typename R>
+__device__ __forceinline__ R from_left(R v)    // lane i <- lane i-1
+{
+    return __shfl_up(v, 1, kWave);
+}
+
+template <typename R>
+__device__ __forceinline__ R from_right(R v)   // lane i <- lane i+1
+{
+    return __shfl_down(v, 1, kWave);
+}
+
+template <typename R>
+__device__ __forceinline__ R from_lane(R v, int src)
+{
+    return __shfl(v, src, kWave);
+}
+
+__device__ __forceinline__ int64_t profile_shift(double bS, double tau)
+{
+    return (int64_t)rint(bS * tau);
+}
+
+__device__ __forceinline__ int64_t clampi(int64_t i, int64_t lo, int64_t hi)
+{
+    return i < lo ? lo : (i > hi ? hi : i);
+}
+
+template <typename R, int C>
+__device__ __forceinline__ void load_cells(const R *__restrict__ p, R (&v)[C])
+{
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[q];
+            v[4 * q + 0] = t.x;
+            v[4 * q + 1] = t.y;
+            v[4 * q + 2] = t.z;
+            v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < C / 2; ++q) {
+            const double2 t = reinterpret_cast<const double2 *>(p)[q];
+            v[2 * q + 0] = t.x;
+            v[2 * q + 1] = t.y;
+        }
+    }
+}
+
+template <typename R, int C>
+__device__ __forceinline__ void store_cells(R *__restrict__ p, const R (&v)[C])
+{
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q)
+            reinterpret_cast<float4 *>(p)[q] =
+                make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < C / 2; ++q)
+            reinterpret_cast<double2 *>(p)[q] = make_double2(v[2 * q], v[2 * q + 1]);
+    }
+}
+
+// Move a lane-distributed coefficient window by d in {-1, 0, +1} cells
+// (d is the same on every lane).  The value entering at a tile edge is
+// not meaningful; it only ever reaches lanes outside the valid region.
+template <typename R, int C>
+__device__ __forceinline__ void shift_window(R (&a)[C], int64_t d)
+{
+    if (d == 1) {
+        const R in = from_left(a[C - 1]);
+#pragma unroll
+        for (int c = C - 1; c > 0; --c)
+            a[c] = a[c - 1];
+        a[0] = in;
+    } else if (d == -1) {
+        const R in = from_right(a[0]);
+#pragma unroll
+        for (int c = 0; c < C - 1; ++c)
+            a[c] = a[c + 1];
+        a[C - 1] = in;
+    }
+}
+
+// a[idx] for a register array and a wave-uniform runtime idx, written as
+// a chain of selects with constant indices only (an indexed read would
+// force the array out of registers).
+template <typename R, int C, int I = C - 1>
+__device__ __forceinline__ R pick(const R (&a)[C], int idx)
+{
+    if constexpr (I == 0)
+        return a[0];
+    else
+        return idx == I ? a[I] : pick<R, C, I - 1>(a, idx);
+}
+
+// ------------------------------------------------------------- the tile
+
+template <typename R, int C, int KIND, bool NEG>
+__device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
+                                          int tile, int64_t block, int T)
+{
+    constexpr bool kMatter = (KIND == GFDTD_MATTER);
+    const int lane = threadIdx.x & (kWave - 1);
+
+    const int64_t nz = rd->nz;
+    const int64_t steps = rd->steps;
+    const int64_t lb = block - rd->start_block;
+    const int64_t n0 = lb * T + 1;
+    if (lb < 0 || n0 > steps)
+        return;
+    const int nsub = (int)((steps - n0 + 1) < T ? (steps - n0 + 1) : T);
+    const bool last = (n0 + nsub - 1 == steps);
+    const int par = (int)(lb & 1);
+
+    const double bS64 = rd->bS;
+    const double beta64 = rd->beta;
+    const R S = (R)rd->S;
+    const R bS = (R)bS64;
+    const R hb = (R)rd->hb;
+    const int hl = rd->hl;
+    const int hr = rd->hr;
+    const int abc = rd->abc;
+    const int nprobe = rd->nprobe;
+    const int64_t W = (int64_t)kWave * C;
+    const int64_t x0 = (int64_t)tile * rd->own_cells - (int64_t)hl * C;
+    const int64_t kb = x0 + (int64_t)lane * C;
+
+    const R *__restrict__ Dsrc = static_cast<const R *>(rd->D[par]);
+    const R *__restrict__ Bsrc = static_cast<const R *>(rd->B[par]);
+    R *__restrict__ Ddst = static_cast<R *>(rd->D[par ^ 1]);
+    R *__restrict__ Bdst = static_cast<R *>(rd->B[par ^ 1]);
+    const R *__restrict__ cEp = static_cast<const R *>(rd->cE);
+    const R *__restrict__ cHp = static_cast<const R *>(rd->cH);
+    const R *__restrict__ gBp = static_cast<const R *>(rd->gB);
+
+    R D[C], B[C];
+    load_cells<R, C>(Dsrc + kb, D);
+    load_cells<R, C>(Bsrc + kb, B);
+
+    // coefficients for the first step of the block: E nodes at n0-1/2,
+    // H nodes at n0
+    int64_t mE = profile_shift(bS64, (double)(n0 - 1) + 0.5);
+    int64_t mH = profile_shift(bS64, (double)n0);
+    R ce[C], ch[C], ge[C], gh[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int64_t iE = clampi(kb + c - mE, 0, nz - 1);
+        const int64_t iH = clampi(kb + c - mH, 0, nz - 2);
+        ce[c] = cEp[iE];
+        ch[c] = cHp[iH];
+        if constexpr (kMatter) {
+            ge[c] = gBp[iE];
+            gh[c] = gBp[iH];
+        }
+    }
+
+    const bool touchL = x0 < 0;              // holds E node 0 (and ghosts)
+    const bool touchR = x0 + W > nz - 1;     // holds node nz-1 (and ghosts)
+
+    // Off the grid B takes the edge value (zero-gradient extension).
+    auto ghosts = [&](R (&Bv)[C]) __attribute__((always_inline)) {
+        if (touchL) {
+            const int l0 = (int)(-x0 / C);
+            const R b0 = from_lane(Bv[0], l0);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (kb + c < 0)
+                    Bv[c] = b0;
+        }
+        if (touchR) {
+            const int64_t r = nz - 2 - x0;
+            const R bl = from_lane(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (kb + c >= nz - 1)
+                    Bv[c] = bl;
+        }
+    };
+    if (touchL || touchR)
+        ghosts(B);
+
+    const int64_t ks = rd->src_cell;
+    const bool hasSrc = rd->nsrc > 0 && ks >= x0 && ks < x0 + W;
+    const int ls = hasSrc ? (int)((ks - x0) / C) : -1;
+    const int cs = hasSrc ? (int)((ks - x0) % C) : 0;
+    const int64_t own_lo = x0 + (int64_t)hl * C;
+    const int64_t own_hi = x0 + W - (int64_t)hr * C;
+
+    R Es[C], sums[C];
+
+    // E* of every cell from the current (D, B) and the E coefficients.
+    auto compute_es = [&]() __attribute__((always_inline)) {
+        if constexpr (!NEG) {
+            const R Bm1 = from_left(B[C - 1]);
+            const R Bm2 = from_left(B[C - 2]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const R b1 = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bm1;
+                const R b2 = (c >= 2) ? B[c >= 2 ? c - 2 : 0] : (c == 1 ? Bm1 : Bm2);
+                sums[c] = b1 + b2;
+            }
+        } else {
+            const R Bp1 = from_right(B[0]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const R b1 = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bp1;
+                sums[c] = b1 + B[c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            if constexpr (kMatter)
+                Es[c] = D[c] * ce[c] - ge[c] * sums[c];
+            else
+                Es[c] = D[c] * ce[c] - hb * sums[c];
+        }
+    };
+
+    // Physical E = E* + beta Bbar at the owned probes, for time n-1/2.
+    auto record = [&](int64_t n) __attribute__((always_inline)) {
+        if (n < 2)
+            return;
+        for (int q = 0; q < nprobe; ++q) {
+            const int64_t kp = rd->probes[q];
+            if (kp < own_lo || kp >= own_hi)
+                continue;
+            const int lp = (int)((kp - x0) / C);
+            const int cp = (int)((kp - x0) % C);
+            const R e = pick<R, C>(Es, cp);
+            const R sm = pick<R, C>(sums, cp);
+            if (lane == lp)
+                rd->trace[(int64_t)q * steps + (n - 2)] =
+                    (double)e + beta64 * (0.5 * (double)sm);
+        }
+    };
+
+    for (int s = 0; s < nsub; ++s) {
+        const int64_t n = n0 + s;
+        if (s > 0) {                      // H coefficients at time n
+            const int64_t m = profile_shift(bS64, (double)n);
+            shift_window<R, C>(ch, m - mH);
+            if constexpr (kMatter)
+                shift_window<R, C>(gh, m - mH);
+            mH = m;
+        }
+
+        compute_es();
+        record(n);
+
+        // (10a) Faraday
+        const R EsR = from_right(Es[0]);
+        const R DR = from_right(D[0]);
+        R Bn[C], Hs[C];
+        if constexpr (!NEG) {
+            const R Bm1 = from_left(B[C - 1]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
+                const R bp = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bm1;
+                Bn[c] = B[c] - S * (esn - Es[c]) - bS * (B[c] - bp);
+            }
+        } else {
+            const R Bp1 = from_right(B[0]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
+                const R bn = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bp1;
+                Bn[c] = B[c] - S * (esn - Es[c]) - bS * (bn - B[c]);
+            }
+        }
+        // (10d) H*
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const R dn = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
+            if constexpr (kMatter)
+                Hs[c] = Bn[c] * ch[c] - gh[c] * (dn + D[c]);
+            else
+                Hs[c] = Bn[c] * ch[c] - hb * (dn + D[c]);
+        }
+        // (10b) Ampere
+        const R HsL = from_left(Hs[C - 1]);
+        const R DL = from_left(D[C - 1]);
+        R Dn[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const R hp = (c >= 1) ? Hs[c >= 1 ? c - 1 : 0] : HsL;
+            if constexpr (!NEG) {
+                const R dp = (c >= 1) ? D[c >= 1 ? c - 1 : 0] : DL;
+                Dn[c] = D[c] - S * (Hs[c] - hp) - bS * (D[c] - dp);
+            } else {
+                const R dn = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
+                Dn[c] = D[c] - S * (Hs[c] - hp) - bS * (dn - D[c]);
+            }
+        }
+        // soft source
+        if (hasSrc && n <= rd->nsrc) {
+            const R g = (R)rd->src[n - 1];
+            if (lane == ls) {
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    if (c == cs)
+                        Dn[c] += g;
+            }
+        }
+        // end nodes, at time n+1/2
+        const int64_t mEn = profile_shift(bS64, (double)n + 0.5);
+        if (touchL) {
+            const int l0 = (int)(-x0 / C);
+            if (lane == l0) {
+                if (abc == GFDTD_ABC_MUR1) {
+                    const R cL = (R)rd->murL[clampi(-mEn, 0, nz - 1)];
+                    Dn[0] = D[1] + cL * (Dn[1] - D[0]);
+                } else {
+                    Dn[0] = (R)0;
+                }
+            }
+        }
+        if (touchR) {
+            const int64_t r = nz - 1 - x0;
+            const int lr = (int)(r / C);
+            const int cr = (int)(r % C);
+            const R dlo = from_left(D[C - 1]);
+            const R dln = from_left(Dn[C - 1]);
+            const R cR = (R)rd->murR[clampi(nz - 1 - mEn, 0, nz - 1)];
+            if (lane == lr) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    if (c == cr) {
+                        const R po = (c >= 1) ? D[c >= 1 ? c - 1 : 0] : dlo;
+                        const R pn = (c >= 1) ? Dn[c >= 1 ? c - 1 : 0] : dln;
+                        Dn[c] = (abc == GFDTD_ABC_MUR1) ? po + cR * (pn - D[c]) : (R)0;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            D[c] = Dn[c];
+            B[c] = Bn[c];
+        }
+        if (touchL || touchR)
+            ghosts(B);
+
+        // E coefficients at time n+1/2 for the next step
+        shift_window<R, C>(ce, mEn - mE);
+        if constexpr (kMatter)
+            shift_window<R, C>(ge, mEn - mE);
+        mE = mEn;
+    }
+
+    if (last) {               // the run ends in this block: E at N+1/2
+        compute_es();
+        record(steps + 1);
+    }
+
+    if (lane >= hl && lane < kWave - hr) {
+        store_cells<R, C>(Ddst + kb, D);
+        store_cells<R, C>(Bdst + kb, B);
+    }
+}
+
+template <typename R, int C, int KIND>
+__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
+    const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
+    int64_t block, int T, int ntiles)
+{
+    const int t = __builtin_amdgcn_readfirstlane(
+        (int)(blockIdx.x * kWavesPerGroup + (threadIdx.x / kWave)));
+    if (t >= ntiles)
+        return;
+    const TileRef ref = tiles[t];
+    const RunDesc *rd = runs + ref.run;
+    if (rd->neg)
+        tile_body<R, C, KIND, true>(rd, ref.tile, block, T);
+    else
+        tile_body<R, C, KIND, false>(rd, ref.tile, block, T);
+}
+
+template <typename R, int KIND>
+static hipError_t launch_tiles_c(int C, const RunDesc *runs,
+                                 const TileRef *tiles, int64_t block, int T,
+                                 int ntiles, hipStream_t stream)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    const dim3 grid((ntiles + kWavesPerGroup - 1) / kWavesPerGroup);
+    const dim3 blk(kWave * kWavesPerGroup);
+    switch (C) {
+    case 4:
+        hipLaunchKernelGGL((k_tiles<R, 4, KIND>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_tiles<R, 8, KIND>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles);
+        break;
+    case 16:
+        hipLaunchKernelGGL((k_tiles<R, 16, KIND>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(int precision, int kind, int C, const RunDesc *runs,
+                        const TileRef *tiles, int64_t block, int T,
+                        int ntiles, hipStream_t stream)
+{
+    if (precision == GFDTD_F32) {
+        return kind == GFDTD_MATTER
+                   ? launch_tiles_c<float, GFDTD_MATTER>(C, runs, tiles, block, T, ntiles, stream)
+                   : launch_tiles_c<float, GFDTD_MODULATION>(C, runs, tiles, block, T, ntiles, stream);
+    }
+    return kind == GFDTD_MATTER
+               ? launch_tiles_c<double, GFDTD_MATTER>(C, runs, tiles, block, T, ntiles, stream)
+               : launch_tiles_c<double, GFDTD_MODULATION>(C, runs, tiles, block, T, ntiles, stream);
+}
+
+// ------------------------------------------------------------- set-up
+
+// Exit speed of a wave leaving through an end (dir = +1 right, -1 left):
+// 1/n in a moving modulation, relativistic addition in moving matter.
+__device__ __forceinline__ double exit_speed(int kind, double n, double beta,
+                                             double dir)
+{
+    if (kind != GFDTD_MATTER)
+        return 1.0 / n;
+    const double b = dir * beta;
+    return (1.0 / n + b) / (1.0 + b / n);
+}
+
+template <typename R>
+__device__ __forceinline__ void prep_cell(const PrepDesc &d, int64_t i)
+{
+    const int64_t nz = d.nz;
+    const double eps = d.eps[i];
+    const double mu = d.mu[i];
+    const double b = d.beta;
+    if (d.kind == GFDTD_MATTER) {
+        const double g = (1.0 - b * b) / (eps * mu - b * b);
+        static_cast<R *>(d.cE)[i] = (R)(g * mu);
+        static_cast<R *>(d.cH)[i] = (R)(g * eps);
+        static_cast<R *>(d.gB)[i] = (R)(g * b * 0.5);
+    } else {
+        static_cast<R *>(d.cE)[i] = (R)(1.0 / eps);
+        static_cast<R *>(d.cH)[i] = (R)(1.0 / mu);
+    }
+    // Mur coefficients (S u - 1)/(S u + 1) for the medium an end node sees
+    // when rest cell i sits under it: the left end pairs E cell i with H
+    // cell i, the right end pairs E cell i with H cell i-1.
+    const double nL = sqrt(eps * d.mu[i < nz - 2 ? i : nz - 2]);
+    const double nR = sqrt(eps * d.mu[i > 0 ? i - 1 : 0]);
+    const double uL = exit_speed(d.kind, nL, b, -1.0);
+    const double uR = exit_speed(d.kind, nR, b, 1.0);
+    d.murL[i] = (d.S * uL - 1.0) / (d.S * uL + 1.0);
+    d.murR[i] = (d.S * uR - 1.0) / (d.S * uR + 1.0);
+    if (i < d.nsrc) {      // modulated Gaussian (App. B.1) at t = (i+1) S
+        const double t = (double)(i + 1) * d.S;
+        const double u = (t - d.t0) / d.tau;
+        d.src[i] = d.amp * sin(d.omega * (t - d.t0) + d.phase) * exp(-u * u);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prep(const PrepDesc *__restrict__ descs)
+{
+    const PrepDesc &d = descs[blockIdx.y];
+    const int64_t n = d.nz > d.nsrc ? d.nz : d.nsrc;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < d.nz) {
+            if (d.precision == GFDTD_F32)
+                prep_cell<float>(d, i);
+            else
+                prep_cell<double>(d, i);
+        } else if (i < d.nsrc) {
+            const double t = (double)(i + 1) * d.S;
+            const double u = (t - d.t0) / d.tau;
+            d.src[i] = d.amp * sin(d.omega * (t - d.t0) + d.phase) * exp(-u * u);
+        }
+    }
+}
+
+hipError_t launch_prep(const PrepDesc *dev_descs, int count, int max_cells,
+                       hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    int bx = (max_cells + 255) / 256;
+    bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+    hipLaunchKernelGGL(k_prep, dim3(bx, count), dim3(256), 0, stream, dev_descs);
+    return hipGetLastError();
+}
+
+// Zero both halves of every field pair, padding included (a plain fill
+// kernel: usable inside captured graphs).
+__global__ __launch_bounds__(256) void k_zero(const PrepDesc *__restrict__ descs,
+                                              int word)
+{
+    const PrepDesc &d = descs[blockIdx.y];
+    const int64_t words16 = d.field_cells * word / 16;
+    for (int f = 0; f < 4; ++f) {
+        uint4 *p = reinterpret_cast<uint4 *>(static_cast<char *>(d.fields[f]) -
+                                             kPad * word);
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+             i < words16; i += (int64_t)gridDim.x * blockDim.x)
+            p[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+hipError_t launch_zero(const PrepDesc *dev_descs, int count,
+                       int64_t max_field_cells, int precision,
+                       hipStream_t stream)
+{
+    if (count <= 0)
+        return hipSuccess;
+    const int word = precision == GFDTD_F32 ? 4 : 8;
+    int64_t bx = (max_field_cells * word / 16 + 255) / 256;
+    bx = bx < 1 ? 1 : (bx > 512 ? 512 : bx);
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)bx, count), dim3(256), 0, stream,
+                       dev_descs, word);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- probe DFT
+
+// X(w) = sum_n E_n S exp(+i w t_n), t_n = (n + 1/2) S, in FP64; one block
+// per (run, probe, frequency), a fixed-order reduction.
+__global__ __launch_bounds__(256) void k_dft(const DftDesc *__restrict__ descs)
+{
+    const DftDesc &d = descs[blockIdx.y];
+    const int pf = blockIdx.x;
+    if (pf >= d.nprobe * d.nfreq)
+        return;
+    const int q = pf / d.nfreq;
+    const int f = pf % d.nfreq;
+    const double w = d.omegas[f];
+    const double *tr = d.trace + (int64_t)q * d.steps;
+    double re = 0.0, im = 0.0;
+    for (int64_t i = threadIdx.x; i < d.steps; i += blockDim.x) {
+        const double t = ((double)(i + 1) + 0.5) * d.S;
+        double s, c;
+        sincos(w * t, &s, &c);
+        const double e = tr[i] * d.S;
+        re += e * c;
+        im += e * s;
+    }
+    __shared__ double sre[256];
+    __shared__ double sim[256];
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sre[threadIdx.x] += sre[threadIdx.x + h];
+            sim[threadIdx.x] += sim[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.out[2 * pf] = sre[0];
+        d.out[2 * pf + 1] = sim[0];
+    }
+}
+
+hipError_t launch_dft(const DftDesc *dev_descs, int count, int max_pf,
+                      hipStream_t stream)
+{
+    if (count <= 0 || max_pf <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_dft, dim3(max_pf, count), dim3(256), 0, stream, dev_descs);
+    return hipGetLastError();
+}
+
+}  // namespace gfdtd

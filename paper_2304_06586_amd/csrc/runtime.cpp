@@ -1,0 +1,917 @@
+// Host runtime of the generalized-FDTD library: argument validation, the
+// stability pre-flight, workspace carving, batch plans (run tables, tile
+// tables, launch sequences, optional hipGraph capture) and the C-ABI
+// entry points.  The continuous-batching server lives in server.cpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "gfdtd.h"
+#include "gfdtd_internal.h"
+#include "runtime.h"
+
+namespace gfdtd {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_error;
+
+gfdtd_status fail(gfdtd_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return s;
+}
+
+gfdtd_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(GFDTD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_error.clear(); }
+const char *last_error() { return g_error.c_str(); }
+
+// -------------------------------------------------------------- validation
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
+{
+    if (!p)
+        return fail(GFDTD_E_INVALID, "problem is NULL");
+    if (p->struct_size < sizeof(gfdtd_problem))
+        return fail(GFDTD_E_INVALID, "problem struct_size %u < %zu",
+                    p->struct_size, sizeof(gfdtd_problem));
+    if (p->kind != GFDTD_MODULATION && p->kind != GFDTD_MATTER)
+        return fail(GFDTD_E_INVALID, "unknown kind %d", p->kind);
+    if (p->precision != GFDTD_F32 && p->precision != GFDTD_F64)
+        return fail(GFDTD_E_INVALID, "unknown precision %d", p->precision);
+    if (p->abc != GFDTD_ABC_MUR1 && p->abc != GFDTD_ABC_PEC)
+        return fail(p->abc == 2 ? GFDTD_E_UNSUPPORTED : GFDTD_E_INVALID,
+                    "end condition %d not available", p->abc);
+    if (p->nz < 8)
+        return fail(GFDTD_E_INVALID, "nz = %lld < 8", (long long)p->nz);
+    if (p->nz > (int64_t(1) << 31))
+        return fail(GFDTD_E_INVALID, "nz = %lld too large", (long long)p->nz);
+    if (steps < 0)
+        return fail(GFDTD_E_INVALID, "steps = %lld < 0", (long long)steps);
+    if (!finite_pos(p->courant))
+        return fail(GFDTD_E_INVALID, "Courant number must be finite and > 0");
+    if (!std::isfinite(p->beta) || std::fabs(p->beta) >= 1.0)
+        return fail(GFDTD_E_INVALID, "|beta| must be < 1");
+    if (std::fabs(p->beta * p->courant) >= 1.0)
+        return fail(GFDTD_E_INVALID, "|beta| S must be < 1");
+    if (!p->eps_rest || !p->mu_rest)
+        return fail(GFDTD_E_INVALID, "eps_rest / mu_rest missing");
+    for (int64_t i = 0; i < p->nz; ++i)
+        if (!finite_pos(p->eps_rest[i]) || !finite_pos(p->mu_rest[i]))
+            return fail(GFDTD_E_INVALID, "eps_rest/mu_rest[%lld] not finite > 0",
+                        (long long)i);
+    if (p->src_cell < 1 || p->src_cell > p->nz - 2)
+        return fail(GFDTD_E_INVALID, "src_cell %lld outside 1..nz-2",
+                    (long long)p->src_cell);
+    if (!std::isfinite(p->src_amp) || !std::isfinite(p->src_omega) ||
+        !std::isfinite(p->src_t0) || !std::isfinite(p->src_phase) ||
+        !std::isfinite(p->src_t_off))
+        return fail(GFDTD_E_INVALID, "source parameters must be finite");
+    if (p->src_amp != 0.0 && !finite_pos(p->src_tau))
+        return fail(GFDTD_E_INVALID, "src_tau must be > 0");
+    if (p->nprobe < 0 || p->nprobe > GFDTD_MAX_PROBES)
+        return fail(GFDTD_E_INVALID, "nprobe %d outside 0..%d", p->nprobe,
+                    GFDTD_MAX_PROBES);
+    if (p->nprobe > 0 && !p->probe_cells)
+        return fail(GFDTD_E_INVALID, "probe_cells missing");
+    for (int q = 0; q < p->nprobe; ++q)
+        if (p->probe_cells[q] < 0 || p->probe_cells[q] >= p->nz)
+            return fail(GFDTD_E_INVALID, "probe %d at %lld outside the grid", q,
+                        (long long)p->probe_cells[q]);
+    if (p->nfreq < 0 || (p->nfreq > 0 && !p->omegas))
+        return fail(GFDTD_E_INVALID, "bad nfreq / omegas");
+    for (int f = 0; f < p->nfreq; ++f)
+        if (!std::isfinite(p->omegas[f]))
+            return fail(GFDTD_E_INVALID, "omegas[%d] not finite", f);
+    return GFDTD_OK;
+}
+
+// ------------------------------------------------------ stability pre-flight
+
+// Largest |eigenvalue| over theta of the one-step amplification matrix of
+// the scheme in a uniform medium with eps' mu' = n2 (Section 5, App. A).
+// A plane wave D_k = D exp(i theta k), B_{k+1/2} = B exp(i theta (k+1/2))
+// is pushed through (10c), (10a), (10d), (10b) with the Table 1 terms.
+static double spectral_radius(double n2, double S, double beta, int kind,
+                              int ntheta)
+{
+    using cd = std::complex<double>;
+    double aE, aH, bE, bH;
+    if (kind == GFDTD_MATTER) {
+        const double g = (1.0 - beta * beta) / (n2 - beta * beta);
+        aE = g;          // with mu' = 1 the product below only needs n2
+        aH = g * n2;
+        bE = bH = g * beta;
+    } else {
+        aE = 1.0 / n2;
+        aH = 1.0;
+        bE = bH = beta;
+    }
+    const bool colA = beta >= 0.0;
+    double best = 0.0;
+    for (int t = 1; t <= ntheta; ++t) {
+        const double th = M_PI * t / ntheta;
+        const cd h = std::polar(1.0, 0.5 * th);          // e^{i th/2}
+        const cd e1 = h * h;                             // e^{i th}
+        const cd curl = h - 1.0 / h;
+        const cd bbar = colA ? 0.5 * (1.0 / h + 1.0 / (h * e1)) : 0.5 * (h * e1 + h);
+        const cd dlt = colA ? 1.0 - 1.0 / e1 : e1 - 1.0;
+        const cd dbar = 0.5 * (h + 1.0 / h);
+        cd G[2][2];
+        for (int col = 0; col < 2; ++col) {
+            const cd D = col == 0 ? 1.0 : 0.0;
+            const cd B = col == 1 ? 1.0 : 0.0;
+            const cd Es = aE * D - bE * bbar * B;
+            const cd Bn = B - S * curl * Es - beta * S * dlt * B;
+            const cd Hs = aH * Bn - bH * dbar * D;
+            const cd Dn = D - S * curl * Hs - beta * S * dlt * D;
+            G[0][col] = Dn;
+            G[1][col] = Bn;
+        }
+        const cd tr = G[0][0] + G[1][1];
+        const cd det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+        const cd disc = std::sqrt(tr * tr - 4.0 * det);
+        best = std::max(best, std::max(std::abs(0.5 * (tr + disc)),
+                                       std::abs(0.5 * (tr - disc))));
+    }
+    return best;
+}
+
+// The one-step matrix depends on the medium only through eps' mu' (for a
+// modulation through 1/(eps mu) and for matter through g), so distinct
+// products are scanned: all of them when few, else the extremes and 255
+// quantiles.
+gfdtd_status preflight(const gfdtd_problem *p, double *growth)
+{
+    std::vector<double> n2(p->nz);
+    for (int64_t i = 0; i < p->nz; ++i)
+        n2[i] = p->eps_rest[i] * p->mu_rest[i];
+    std::sort(n2.begin(), n2.end());
+    n2.erase(std::unique(n2.begin(), n2.end()), n2.end());
+    std::vector<double> pick;
+    if (n2.size() <= 256) {
+        pick = n2;
+    } else {
+        for (int q = 0; q < 256; ++q)
+            pick.push_back(n2[(size_t)((n2.size() - 1) * (double)q / 255.0)]);
+    }
+    double g = 0.0;
+    for (double v : pick)
+        g = std::max(g, spectral_radius(v, p->courant, p->beta, p->kind, 512));
+    if (growth)
+        *growth = g;
+    if (g > 1.0 + 1e-9 && !(p->flags & GFDTD_FLAG_ALLOW_UNSTABLE))
+        return fail(GFDTD_E_UNSTABLE,
+                    "pre-flight: amplification factor %.12g > 1 (beta %.4g, "
+                    "S %.4g, largest eps'mu' %.4g)",
+                    g, p->beta, p->courant, n2.back());
+    return GFDTD_OK;
+}
+
+// ------------------------------------------------------------------ layout
+
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t Carver::take(size_t bytes)
+{
+    off = round_up(off, 256);
+    const size_t r = off;
+    off += round_up(bytes, 256);
+    return r;
+}
+
+int64_t source_samples(const gfdtd_problem *p, int64_t steps)
+{
+    if (p->src_amp == 0.0 || steps <= 0)
+        return 0;
+    // largest n <= steps with n S <= t_off, with the same FP test as the
+    // per-step rule
+    double est = std::floor(p->src_t_off / p->courant);
+    int64_t n = est < 0 ? 0 : (int64_t)std::min<double>(est, (double)steps);
+    while (n < steps && (double)(n + 1) * p->courant <= p->src_t_off)
+        ++n;
+    while (n > 0 && !((double)n * p->courant <= p->src_t_off))
+        --n;
+    return n;
+}
+
+int64_t field_cells(int64_t nz) { return (int64_t)round_up((size_t)(nz + 2 * kPad), 64); }
+
+void carve_run(Carver &cv, const gfdtd_problem *p, int64_t steps, RunLayout &L)
+{
+    const size_t w = p->precision == GFDTD_F32 ? 4 : 8;
+    const size_t nz = (size_t)p->nz;
+    L.eps = cv.take(nz * 8);
+    L.mu = cv.take(nz * 8);
+    L.cE = cv.take(nz * w);
+    L.cH = cv.take(nz * w);
+    L.gB = p->kind == GFDTD_MATTER ? cv.take(nz * w) : 0;
+    L.murL = cv.take(nz * 8);
+    L.murR = cv.take(nz * 8);
+    L.nsrc = source_samples(p, steps);
+    L.src = cv.take((size_t)std::max<int64_t>(L.nsrc, 1) * 8);
+    L.probes = cv.take((size_t)std::max(p->nprobe, 1) * 8);
+    L.omegas = cv.take((size_t)std::max(p->nfreq, 1) * 8);
+    L.trace = cv.take((size_t)std::max<int64_t>((int64_t)p->nprobe * steps, 1) * 8);
+    L.dft = cv.take((size_t)std::max(p->nprobe * p->nfreq, 1) * 16);
+    const size_t fb = (size_t)field_cells(p->nz) * w;
+    for (int f = 0; f < 4; ++f)
+        L.field[f] = cv.take(fb);
+}
+
+size_t table_bytes(int nruns, int64_t max_tiles)
+{
+    Carver cv;
+    cv.take((size_t)nruns * sizeof(RunDesc));
+    cv.take((size_t)std::max<int64_t>(max_tiles, 1) * sizeof(TileRef));
+    cv.take((size_t)nruns * sizeof(PrepDesc));
+    cv.take((size_t)nruns * sizeof(DftDesc));
+    return cv.off;
+}
+
+// Upper bound of wave tiles of one run for any tiling (C >= 4, at least
+// one owned lane).
+int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
+
+// --------------------------------------------------------------- tiling
+
+void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
+                   int &C, int &T)
+{
+    const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
+    C = (ex && ex->cells_per_lane) ? ex->cells_per_lane
+                                   : (precision == GFDTD_F32 ? 16 : 8);
+    if (variant == GFDTD_VARIANT_STEP)
+        T = 1;
+    else if (ex && ex->block_steps > 0)
+        T = ex->block_steps;
+    else
+        T = 16;
+    if (max_steps > 0 && T > max_steps)
+        T = (int)std::max<int64_t>(1, max_steps);
+}
+
+bool halo_lanes(double beta, int C, int T, int &hl, int &hr)
+{
+    const int up = (3 * T + C - 1) / C, one = (T + C - 1) / C, two = (2 * T + C - 1) / C;
+    if (beta >= 0.0) {
+        hl = up;
+        hr = one;
+    } else {
+        hl = one;
+        hr = two;
+    }
+    return hl + hr < kWave;
+}
+
+// ------------------------------------------------------------------- batch
+
+gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
+                            int32_t count, const gfdtd_exec *ex, void *ws_,
+                            size_t ws_bytes_, hipStream_t stream_)
+{
+    stream = stream_;
+    ws = static_cast<char *>(ws_);
+    ws_bytes = ws_bytes_;
+    if (count < 0 || (count > 0 && (!probs || !steps_in)))
+        return fail(GFDTD_E_INVALID, "bad batch arguments");
+    if (ex && ex->struct_size < sizeof(gfdtd_exec))
+        return fail(GFDTD_E_INVALID, "exec struct_size too small");
+    if (ex && ex->cells_per_lane && ex->cells_per_lane != 4 &&
+        ex->cells_per_lane != 8 && ex->cells_per_lane != 16)
+        return fail(GFDTD_E_INVALID, "cells_per_lane must be 4, 8 or 16");
+    if (ex && (ex->block_steps < 0 || ex->block_steps > 256))
+        return fail(GFDTD_E_INVALID, "block_steps outside 0..256");
+    runs.resize(count);
+    for (int i = 0; i < count; ++i) {
+        gfdtd_status st = validate(&probs[i], steps_in[i]);
+        if (st != GFDTD_OK)
+            return fail(st, "run %d: %s", i, last_error());
+        st = preflight(&probs[i], nullptr);
+        if (st != GFDTD_OK)
+            return fail(st, "run %d: %s", i, last_error());
+        RunHost &r = runs[i];
+        r.p = probs[i];
+        r.steps = steps_in[i];
+        r.eps.assign(probs[i].eps_rest, probs[i].eps_rest + probs[i].nz);
+        r.mu.assign(probs[i].mu_rest, probs[i].mu_rest + probs[i].nz);
+        r.probes.assign(probs[i].probe_cells, probs[i].probe_cells + probs[i].nprobe);
+        r.omegas.assign(probs[i].omegas, probs[i].omegas + probs[i].nfreq);
+        r.p.eps_rest = r.eps.data();
+        r.p.mu_rest = r.mu.data();
+        r.p.probe_cells = r.probes.data();
+        r.p.omegas = r.omegas.data();
+    }
+    // groups by (precision, kind)
+    Carver cv;
+    for (auto &r : runs)
+        carve_run(cv, &r.p, r.steps, r.L);
+    for (int g = 0; g < 4; ++g) {
+        Group G;
+        G.precision = g >> 1;
+        G.kind = g & 1;
+        int64_t max_steps = 0;
+        for (int i = 0; i < count; ++i)
+            if (runs[i].p.precision == G.precision && runs[i].p.kind == G.kind) {
+                G.members.push_back(i);
+                max_steps = std::max(max_steps, runs[i].steps);
+            }
+        if (G.members.empty())
+            continue;
+        choose_tiling(G.precision, ex, max_steps, G.C, G.T);
+        for (int i : G.members)
+            runs[i].T = G.T;
+        int64_t maxt = 0;
+        for (int i : G.members)
+            maxt += max_tiles_of(runs[i].p.nz);
+        G.table_off = cv.take(table_bytes((int)G.members.size(), maxt));
+        groups.push_back(G);
+    }
+    if (cv.off > ws_bytes)
+        return fail(GFDTD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, cv.off);
+    if (count > 0 && !ws)
+        return fail(GFDTD_E_INVALID, "workspace pointer is NULL");
+    use_graph = ex ? ex->use_graph : -1;
+
+    hipError_t e;
+    // uploads
+    for (auto &r : runs) {
+        const size_t nz = (size_t)r.p.nz;
+        if ((e = hipMemcpyAsync(ws + r.L.eps, r.eps.data(), nz * 8, hipMemcpyHostToDevice, stream)) ||
+            (e = hipMemcpyAsync(ws + r.L.mu, r.mu.data(), nz * 8, hipMemcpyHostToDevice, stream)))
+            return hip_fail(e, "upload rest profile");
+        if (r.p.nprobe &&
+            (e = hipMemcpyAsync(ws + r.L.probes, r.probes.data(), r.probes.size() * 8,
+                                hipMemcpyHostToDevice, stream)))
+            return hip_fail(e, "upload probes");
+        if (r.p.nfreq &&
+            (e = hipMemcpyAsync(ws + r.L.omegas, r.omegas.data(), r.omegas.size() * 8,
+                                hipMemcpyHostToDevice, stream)))
+            return hip_fail(e, "upload omegas");
+    }
+    // per-group descriptor tables
+    for (auto &G : groups) {
+        const int nr = (int)G.members.size();
+        // longest runs first, so the live runs of any block are a prefix
+        std::stable_sort(G.members.begin(), G.members.end(), [&](int a, int b) {
+            return runs[a].steps > runs[b].steps;
+        });
+        std::vector<RunDesc> rd(nr);
+        std::vector<PrepDesc> pd(nr);
+        std::vector<DftDesc> dd(nr);
+        std::vector<TileRef> tiles;
+        G.blocks_of.resize(nr);
+        G.tiles_prefix.assign(nr + 1, 0);
+        const size_t w = G.precision == GFDTD_F32 ? 4 : 8;
+        G.max_cells = 0;
+        G.max_field = 0;
+        G.max_pf = 0;
+        for (int m = 0; m < nr; ++m) {
+            RunHost &r = runs[G.members[m]];
+            int hl, hr;
+            if (!halo_lanes(r.p.beta, G.C, G.T, hl, hr))
+                return fail(GFDTD_E_INVALID,
+                            "block of %d steps too deep for %d cells per lane",
+                            G.T, G.C);
+            const int64_t own = (int64_t)(kWave - hl - hr) * G.C;
+            const int64_t nt = (r.p.nz + own - 1) / own;
+            fill_desc(r, G, hl, hr, own, 0, rd[m], pd[m], dd[m]);
+            for (int64_t t = 0; t < nt; ++t)
+                tiles.push_back(TileRef{m, (int32_t)t});
+            G.tiles_prefix[m + 1] = G.tiles_prefix[m] + nt;
+            G.blocks_of[m] = (r.steps + G.T - 1) / G.T;
+            G.max_cells = std::max<int64_t>(G.max_cells, std::max(r.p.nz, r.L.nsrc));
+            G.max_field = std::max<int64_t>(G.max_field, field_cells(r.p.nz));
+            G.max_pf = std::max(G.max_pf, r.p.nprobe * r.p.nfreq);
+            (void)w;
+        }
+        G.nblocks = nr ? G.blocks_of[0] : 0;
+        Carver tc;
+        tc.off = G.table_off;
+        G.runs_off = tc.take((size_t)nr * sizeof(RunDesc));
+        G.tiles_off = tc.take(std::max<size_t>(tiles.size(), 1) * sizeof(TileRef));
+        G.prep_off = tc.take((size_t)nr * sizeof(PrepDesc));
+        G.dft_off = tc.take((size_t)nr * sizeof(DftDesc));
+        G.host_rd = rd;
+        G.host_pd = pd;
+        G.host_dd = dd;
+        G.host_tiles = tiles;
+        if ((e = hipMemcpyAsync(ws + G.runs_off, G.host_rd.data(), nr * sizeof(RunDesc),
+                                hipMemcpyHostToDevice, stream)) ||
+            (e = hipMemcpyAsync(ws + G.tiles_off, G.host_tiles.data(),
+                                G.host_tiles.size() * sizeof(TileRef),
+                                hipMemcpyHostToDevice, stream)) ||
+            (e = hipMemcpyAsync(ws + G.prep_off, G.host_pd.data(), nr * sizeof(PrepDesc),
+                                hipMemcpyHostToDevice, stream)) ||
+            (e = hipMemcpyAsync(ws + G.dft_off, G.host_dd.data(), nr * sizeof(DftDesc),
+                                hipMemcpyHostToDevice, stream)))
+            return hip_fail(e, "upload run tables");
+        if ((e = launch_prep(reinterpret_cast<const PrepDesc *>(ws + G.prep_off), nr,
+                             (int)std::min<int64_t>(G.max_cells, 1 << 30), stream)))
+            return hip_fail(e, "launch set-up kernel");
+    }
+    if ((e = hipStreamSynchronize(stream)))
+        return hip_fail(e, "prepare");
+    for (auto &r : runs)
+        cell_updates += (double)r.p.nz * (double)r.steps;
+    if ((e = hipEventCreate(&ev[0])) || (e = hipEventCreate(&ev[1])) ||
+        (e = hipEventCreate(&ev[2])) || (e = hipEventCreate(&ev[3])))
+        return hip_fail(e, "create events");
+    // launch statistics of one pass
+    for (auto &G : groups)
+        for (int64_t b = 0; b < G.nblocks; ++b) {
+            launches += 1;
+            tiles_total += live_tiles(G, b);
+        }
+    if (use_graph == 1 || (use_graph < 0 && auto_graph()))
+        return build_graphs();
+    return GFDTD_OK;
+}
+
+void Batch::fill_desc(RunHost &r, const Group &G, int hl, int hr, int64_t own,
+                      int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd)
+{
+    fill_run_desc(ws, r, G.precision, hl, hr, own, start_block, rd, pd, dd);
+}
+
+void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
+                   int64_t own, int64_t start_block, RunDesc &rd, PrepDesc &pd,
+                   DftDesc &dd)
+{
+    const size_t w = precision == GFDTD_F32 ? 4 : 8;
+    const gfdtd_problem &p = r.p;
+    std::memset(&rd, 0, sizeof rd);
+    rd.nz = p.nz;
+    rd.steps = r.steps;
+    rd.start_block = start_block;
+    rd.nsrc = r.L.nsrc;
+    rd.src_cell = p.src_cell;
+    rd.own_cells = own;
+    rd.S = p.courant;
+    rd.beta = p.beta;
+    rd.bS = p.beta * p.courant;
+    rd.hb = 0.5 * p.beta;
+    rd.neg = p.beta < 0.0;
+    rd.hl = hl;
+    rd.hr = hr;
+    rd.nprobe = p.nprobe;
+    rd.abc = p.abc;
+    for (int f = 0; f < 2; ++f) {
+        rd.D[f] = base + r.L.field[f] + kPad * w;
+        rd.B[f] = base + r.L.field[2 + f] + kPad * w;
+    }
+    rd.cE = base + r.L.cE;
+    rd.cH = base + r.L.cH;
+    rd.gB = p.kind == GFDTD_MATTER ? base + r.L.gB : nullptr;
+    rd.murL = reinterpret_cast<const double *>(base + r.L.murL);
+    rd.murR = reinterpret_cast<const double *>(base + r.L.murR);
+    rd.src = reinterpret_cast<const double *>(base + r.L.src);
+    rd.probes = reinterpret_cast<const int64_t *>(base + r.L.probes);
+    rd.trace = reinterpret_cast<double *>(base + r.L.trace);
+
+    std::memset(&pd, 0, sizeof pd);
+    pd.nz = p.nz;
+    pd.nsrc = r.L.nsrc;
+    pd.S = p.courant;
+    pd.beta = p.beta;
+    pd.amp = p.src_amp;
+    pd.omega = p.src_omega;
+    pd.t0 = p.src_t0;
+    pd.tau = p.src_tau;
+    pd.phase = p.src_phase;
+    pd.kind = p.kind;
+    pd.precision = p.precision;
+    pd.eps = reinterpret_cast<const double *>(base + r.L.eps);
+    pd.mu = reinterpret_cast<const double *>(base + r.L.mu);
+    pd.cE = base + r.L.cE;
+    pd.cH = base + r.L.cH;
+    pd.gB = p.kind == GFDTD_MATTER ? base + r.L.gB : nullptr;
+    pd.murL = reinterpret_cast<double *>(base + r.L.murL);
+    pd.murR = reinterpret_cast<double *>(base + r.L.murR);
+    pd.src = reinterpret_cast<double *>(base + r.L.src);
+    pd.fields[0] = rd.D[0];
+    pd.fields[1] = rd.D[1];
+    pd.fields[2] = rd.B[0];
+    pd.fields[3] = rd.B[1];
+    pd.field_cells = field_cells(p.nz);
+
+    std::memset(&dd, 0, sizeof dd);
+    dd.steps = r.steps;
+    dd.S = p.courant;
+    dd.nprobe = p.nprobe;
+    dd.nfreq = p.nfreq;
+    dd.trace = rd.trace;
+    dd.omegas = reinterpret_cast<const double *>(base + r.L.omegas);
+    dd.out = reinterpret_cast<double *>(base + r.L.dft);
+}
+
+int Batch::live_tiles(const Group &G, int64_t b) const
+{
+    // members are sorted by step count, so the live ones form a prefix
+    int lo = 0, hi = (int)G.members.size();
+    while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (G.blocks_of[mid] > b)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (int)G.tiles_prefix[lo];
+}
+
+bool Batch::auto_graph() const
+{
+    // plain launches cost a few microseconds each; a graph pays off when
+    // launches are many and each is short
+    double updates_per_launch = launches ? cell_updates / (double)launches : 0.0;
+    return launches >= 64 && updates_per_launch < 2e7;
+}
+
+gfdtd_status Batch::enqueue_zero(hipStream_t s)
+{
+    for (auto &G : groups) {
+        hipError_t e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + G.prep_off),
+                                   (int)G.members.size(), G.max_field, G.precision, s);
+        if (e)
+            return hip_fail(e, "launch zero fill");
+    }
+    return GFDTD_OK;
+}
+
+gfdtd_status Batch::enqueue_steps(hipStream_t s)
+{
+    int64_t nb = 0;
+    for (auto &G : groups)
+        nb = std::max(nb, G.nblocks);
+    for (int64_t b = 0; b < nb; ++b)
+        for (auto &G : groups) {
+            if (b >= G.nblocks)
+                continue;
+            hipError_t e = launch_tiles(G.precision, G.kind, G.C,
+                                        reinterpret_cast<const RunDesc *>(ws + G.runs_off),
+                                        reinterpret_cast<const TileRef *>(ws + G.tiles_off),
+                                        b, G.T, live_tiles(G, b), s);
+            if (e)
+                return hip_fail(e, "launch step kernel");
+        }
+    return GFDTD_OK;
+}
+
+gfdtd_status Batch::enqueue_dft(hipStream_t s)
+{
+    for (auto &G : groups) {
+        hipError_t e = launch_dft(reinterpret_cast<const DftDesc *>(ws + G.dft_off),
+                                  (int)G.members.size(), G.max_pf, s);
+        if (e)
+            return hip_fail(e, "launch DFT kernel");
+    }
+    return GFDTD_OK;
+}
+
+gfdtd_status Batch::build_graphs()
+{
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)))
+        return hip_fail(e, "create capture stream");
+    for (int k = 0; k < 3; ++k) {
+        if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed)))
+            return hip_fail(e, "begin capture");
+        gfdtd_status st = k == 0 ? enqueue_zero(cap_stream)
+                          : k == 1 ? enqueue_steps(cap_stream)
+                                   : enqueue_dft(cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
+        if (st != GFDTD_OK)
+            return st;
+        if (e2)
+            return hip_fail(e2, "end capture");
+        graphs[k] = g;
+        if ((e = hipGraphInstantiate(&execs[k], g, nullptr, nullptr, 0)))
+            return hip_fail(e, "instantiate graph");
+    }
+    graph_on = true;
+    return GFDTD_OK;
+}
+
+gfdtd_status Batch::run()
+{
+    hipError_t e;
+    if ((e = hipEventRecord(ev[0], stream)))
+        return hip_fail(e, "record event");
+    gfdtd_status st;
+    if (graph_on) {
+        if ((e = hipGraphLaunch(execs[0], stream)))
+            return hip_fail(e, "launch zero graph");
+    } else if ((st = enqueue_zero(stream)) != GFDTD_OK) {
+        return st;
+    }
+    (void)hipEventRecord(ev[1], stream);
+    if (graph_on) {
+        if ((e = hipGraphLaunch(execs[1], stream)))
+            return hip_fail(e, "launch step graph");
+    } else if ((st = enqueue_steps(stream)) != GFDTD_OK) {
+        return st;
+    }
+    (void)hipEventRecord(ev[2], stream);
+    if (graph_on) {
+        if ((e = hipGraphLaunch(execs[2], stream)))
+            return hip_fail(e, "launch DFT graph");
+    } else if ((st = enqueue_dft(stream)) != GFDTD_OK) {
+        return st;
+    }
+    if ((e = hipEventRecord(ev[3], stream)))
+        return hip_fail(e, "record event");
+    ran = true;
+    return GFDTD_OK;
+}
+
+gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *out_in,
+                          hipStream_t stream, gfdtd_result *out)
+{
+    (void)out_in;
+    hipError_t e;
+    const gfdtd_problem &p = r.p;
+    const int np = p.nprobe, nf = p.nfreq;
+    std::vector<double> dft((size_t)np * nf * 2);
+    if (np * nf > 0 &&
+        (e = hipMemcpyAsync(dft.data(), ws + r.L.dft, dft.size() * 8,
+                            hipMemcpyDeviceToHost, stream)))
+        return hip_fail(e, "copy DFT");
+    std::vector<double> trace;
+    const bool want_trace = out->trace && (p.flags & GFDTD_FLAG_RECORD_TRACE);
+    // the trace is always read back for the blow-up check when present
+    if (np > 0 && r.steps > 0) {
+        trace.resize((size_t)np * r.steps);
+        if ((e = hipMemcpyAsync(trace.data(), ws + r.L.trace, trace.size() * 8,
+                                hipMemcpyDeviceToHost, stream)))
+            return hip_fail(e, "copy trace");
+    }
+    const size_t w = p.precision == GFDTD_F32 ? 4 : 8;
+    std::vector<char> fd, fb;
+    const int fin = (int)(((r.steps + r.T - 1) / r.T) & 1);   // buffer of the last write
+    if (out->final_d || out->final_b) {
+        fd.resize((size_t)p.nz * w);
+        fb.resize((size_t)p.nz * w);
+        const char *d = ws + r.L.field[fin] + kPad * w;
+        const char *b = ws + r.L.field[2 + fin] + kPad * w;
+        if ((e = hipMemcpyAsync(fd.data(), d, fd.size(), hipMemcpyDeviceToHost, stream)) ||
+            (e = hipMemcpyAsync(fb.data(), b, fb.size(), hipMemcpyDeviceToHost, stream)))
+            return hip_fail(e, "copy fields");
+    }
+    if ((e = hipStreamSynchronize(stream)))
+        return hip_fail(e, "collect");
+    bool finite = true;
+    for (double v : dft)
+        finite = finite && std::isfinite(v);
+    for (double v : trace)
+        finite = finite && std::isfinite(v);
+    out->run_status = finite ? GFDTD_OK : GFDTD_E_BLOWUP;
+    out->steps_done = r.steps;
+    if (out->dft_re && out->dft_im)
+        for (int i = 0; i < np * nf; ++i) {
+            out->dft_re[i] = dft[2 * i];
+            out->dft_im[i] = dft[2 * i + 1];
+        }
+    if (want_trace && !trace.empty())
+        std::memcpy(out->trace, trace.data(), trace.size() * 8);
+    auto conv = [&](const std::vector<char> &src, double *dst, int64_t n) {
+        for (int64_t i = 0; i < n; ++i)
+            dst[i] = w == 4 ? (double)reinterpret_cast<const float *>(src.data())[i]
+                            : reinterpret_cast<const double *>(src.data())[i];
+    };
+    if (r.steps == 0) {
+        if (out->final_d)
+            std::memset(out->final_d, 0, (size_t)p.nz * 8);
+        if (out->final_b)
+            std::memset(out->final_b, 0, (size_t)p.nz * 8);
+    } else {
+        if (out->final_d)
+            conv(fd, out->final_d, p.nz);
+        if (out->final_b) {
+            conv(fb, out->final_b, p.nz - 1);
+            out->final_b[p.nz - 1] = 0.0;
+        }
+    }
+    return GFDTD_OK;
+}
+
+gfdtd_status Batch::collect(gfdtd_result *outs)
+{
+    if (!ran)
+        return fail(GFDTD_E_INVALID, "collect before run");
+    if (!outs && !runs.empty())
+        return fail(GFDTD_E_INVALID, "outs is NULL");
+    hipError_t e;
+    if ((e = hipStreamSynchronize(stream)))
+        return hip_fail(e, "synchronize");
+    for (size_t i = 0; i < runs.size(); ++i) {
+        if (outs[i].struct_size < sizeof(gfdtd_result))
+            return fail(GFDTD_E_INVALID, "result %zu struct_size too small", i);
+        gfdtd_status st = copy_results(ws, runs[i], nullptr, stream, &outs[i]);
+        if (st != GFDTD_OK)
+            return st;
+    }
+    return GFDTD_OK;
+}
+
+void Batch::stats(gfdtd_stats *s) const
+{
+    s->cells_per_lane = groups.empty() ? 0 : groups[0].C;
+    s->block_steps = groups.empty() ? 0 : groups[0].T;
+    s->graph = graph_on ? 1 : 0;
+    s->launches = launches;
+    s->tiles = tiles_total;
+    s->cell_updates = cell_updates;
+    s->step_ms = 0.0;
+    s->pass_ms = 0.0;
+    if (ran && hipEventSynchronize(ev[3]) == hipSuccess) {
+        float a = 0.f, b = 0.f;
+        (void)hipEventElapsedTime(&a, ev[1], ev[2]);
+        (void)hipEventElapsedTime(&b, ev[0], ev[3]);
+        s->step_ms = a;
+        s->pass_ms = b;
+    }
+}
+
+Batch::~Batch()
+{
+    for (int k = 0; k < 3; ++k) {
+        if (execs[k])
+            (void)hipGraphExecDestroy(execs[k]);
+        if (graphs[k])
+            (void)hipGraphDestroy(graphs[k]);
+    }
+    if (cap_stream)
+        (void)hipStreamDestroy(cap_stream);
+    for (auto &x : ev)
+        if (x)
+            (void)hipEventDestroy(x);
+}
+
+}  // namespace gfdtd
+
+// ======================================================================
+// C-ABI
+// ======================================================================
+using namespace gfdtd;
+
+extern "C" {
+
+const char *gfdtd_status_str(gfdtd_status s)
+{
+    switch (s) {
+    case GFDTD_OK: return "ok";
+    case GFDTD_E_INVALID: return "invalid argument";
+    case GFDTD_E_UNSTABLE: return "unstable (pre-flight)";
+    case GFDTD_E_NOMEM: return "workspace or pool too small";
+    case GFDTD_E_DEVICE: return "device error";
+    case GFDTD_E_NOT_READY: return "not ready";
+    case GFDTD_E_BLOWUP: return "non-finite probe values";
+    case GFDTD_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *gfdtd_last_error(void) { return last_error(); }
+
+gfdtd_status gfdtd_check(const gfdtd_problem *p, double *max_growth)
+{
+    clear_error();
+    gfdtd_status st = validate(p, 0);
+    if (st != GFDTD_OK)
+        return st;
+    return preflight(p, max_growth);
+}
+
+gfdtd_status gfdtd_result_sizes(const gfdtd_problem *p, int64_t steps,
+                                size_t *trace_len, size_t *dft_len)
+{
+    clear_error();
+    gfdtd_status st = validate(p, steps);
+    if (st != GFDTD_OK)
+        return st;
+    if (trace_len)
+        *trace_len = (size_t)p->nprobe * (size_t)steps;
+    if (dft_len)
+        *dft_len = (size_t)p->nprobe * (size_t)p->nfreq;
+    return GFDTD_OK;
+}
+
+gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
+                                         const int64_t *steps, int32_t count,
+                                         size_t *bytes)
+{
+    clear_error();
+    if (!bytes || count < 0 || (count > 0 && (!probs || !steps)))
+        return fail(GFDTD_E_INVALID, "bad arguments");
+    Carver cv;
+    int64_t maxt[4] = {0, 0, 0, 0};
+    int nr[4] = {0, 0, 0, 0};
+    for (int i = 0; i < count; ++i) {
+        gfdtd_status st = validate(&probs[i], steps[i]);
+        if (st != GFDTD_OK)
+            return fail(st, "run %d: %s", i, last_error());
+        RunLayout L;
+        carve_run(cv, &probs[i], steps[i], L);
+        const int g = probs[i].precision * 2 + probs[i].kind;
+        maxt[g] += max_tiles_of(probs[i].nz);
+        nr[g] += 1;
+    }
+    for (int g = 0; g < 4; ++g)
+        if (nr[g])
+            cv.take(table_bytes(nr[g], maxt[g]));
+    *bytes = cv.off;
+    return GFDTD_OK;
+}
+
+gfdtd_status gfdtd_workspace_bytes(const gfdtd_problem *p, int64_t steps, size_t *bytes)
+{
+    return gfdtd_batch_workspace_bytes(p, &steps, 1, bytes);
+}
+
+gfdtd_status gfdtd_batch_prepare(const gfdtd_problem *probs, const int64_t *steps,
+                                 int32_t count, const gfdtd_exec *exec, void *ws,
+                                 size_t ws_bytes, void *stream, gfdtd_batch **out)
+{
+    clear_error();
+    if (!out)
+        return fail(GFDTD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<Batch> b(new Batch);
+    gfdtd_status st = b->prepare(probs, steps, count, exec, ws, ws_bytes,
+                                 static_cast<hipStream_t>(stream));
+    if (st != GFDTD_OK)
+        return st;
+    *out = reinterpret_cast<gfdtd_batch *>(b.release());
+    return GFDTD_OK;
+}
+
+gfdtd_status gfdtd_batch_run(gfdtd_batch *b)
+{
+    clear_error();
+    if (!b)
+        return fail(GFDTD_E_INVALID, "batch is NULL");
+    return reinterpret_cast<Batch *>(b)->run();
+}
+
+gfdtd_status gfdtd_batch_collect(gfdtd_batch *b, gfdtd_result *outs)
+{
+    clear_error();
+    if (!b)
+        return fail(GFDTD_E_INVALID, "batch is NULL");
+    return reinterpret_cast<Batch *>(b)->collect(outs);
+}
+
+gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s)
+{
+    clear_error();
+    if (!b || !s || s->struct_size < sizeof(gfdtd_stats))
+        return fail(GFDTD_E_INVALID, "bad arguments");
+    reinterpret_cast<const Batch *>(b)->stats(s);
+    return GFDTD_OK;
+}
+
+void gfdtd_batch_destroy(gfdtd_batch *b) { delete reinterpret_cast<Batch *>(b); }
+
+gfdtd_status gfdtd_solve_batch(const gfdtd_problem *probs, const int64_t *steps,
+                               int32_t count, void *ws, size_t ws_bytes, void *stream,
+                               gfdtd_result *outs)
+{
+    gfdtd_batch *b = nullptr;
+    gfdtd_status st = gfdtd_batch_prepare(probs, steps, count, nullptr, ws, ws_bytes,
+                                          stream, &b);
+    if (st == GFDTD_OK)
+        st = gfdtd_batch_run(b);
+    if (st == GFDTD_OK)
+        st = gfdtd_batch_collect(b, outs);
+    gfdtd_batch_destroy(b);
+    return st;
+}
+
+gfdtd_status gfdtd_solve(const gfdtd_problem *p, int64_t steps, void *ws,
+                         size_t ws_bytes, void *stream, gfdtd_result *out)
+{
+    return gfdtd_solve_batch(p, &steps, 1, ws, ws_bytes, stream, out);
+}
+
+}  // extern "C"

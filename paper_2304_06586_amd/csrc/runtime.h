@@ -1,0 +1,112 @@
+// Host-side structures of the generalized-FDTD runtime (not part of the
+// C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "gfdtd.h"
+#include "gfdtd_internal.h"
+
+namespace gfdtd {
+
+gfdtd_status fail(gfdtd_status s, const char *fmt, ...);
+gfdtd_status hip_fail(hipError_t e, const char *what);
+void clear_error();
+const char *last_error();
+
+gfdtd_status validate(const gfdtd_problem *p, int64_t steps);
+gfdtd_status preflight(const gfdtd_problem *p, double *growth);
+
+// Bump allocator over a workspace, 256-byte aligned.
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes);
+};
+
+// Byte offsets of one run's device arrays inside a workspace.
+struct RunLayout {
+    size_t eps = 0, mu = 0, cE = 0, cH = 0, gB = 0, murL = 0, murR = 0;
+    size_t src = 0, probes = 0, omegas = 0, trace = 0, dft = 0;
+    size_t field[4] = {0, 0, 0, 0};   // D0, D1, B0, B1 (padded)
+    int64_t nsrc = 0;
+};
+
+int64_t source_samples(const gfdtd_problem *p, int64_t steps);
+int64_t field_cells(int64_t nz);
+void carve_run(Carver &cv, const gfdtd_problem *p, int64_t steps, RunLayout &L);
+size_t table_bytes(int nruns, int64_t max_tiles);
+int64_t max_tiles_of(int64_t nz);
+void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
+                   int &C, int &T);
+bool halo_lanes(double beta, int C, int T, int &hl, int &hr);
+
+// A run with host copies of its inputs.
+struct RunHost {
+    gfdtd_problem p{};
+    int64_t steps = 0;
+    int T = 1;                  // block depth of its group
+    std::vector<double> eps, mu, omegas;
+    std::vector<int64_t> probes;
+    RunLayout L;
+};
+
+void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
+                   int64_t own, int64_t start_block, RunDesc &rd, PrepDesc &pd,
+                   DftDesc &dd);
+
+gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *unused,
+                          hipStream_t stream, gfdtd_result *out);
+
+// Runs of one precision and kind, stepped by one kernel instantiation.
+struct Group {
+    int precision = 0, kind = 0, C = 16, T = 16;
+    std::vector<int> members;         // run indices, longest first
+    std::vector<int64_t> blocks_of;   // blocks per member
+    std::vector<int64_t> tiles_prefix;
+    int64_t nblocks = 0;
+    int64_t max_cells = 0, max_field = 0;
+    int max_pf = 0;
+    size_t table_off = 0, runs_off = 0, tiles_off = 0, prep_off = 0, dft_off = 0;
+    std::vector<RunDesc> host_rd;
+    std::vector<PrepDesc> host_pd;
+    std::vector<DftDesc> host_dd;
+    std::vector<TileRef> host_tiles;
+};
+
+struct Batch {
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<RunHost> runs;
+    std::vector<Group> groups;
+    int use_graph = -1;
+    bool graph_on = false;
+    bool ran = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graphs[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t execs[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int64_t launches = 0, tiles_total = 0;
+    double cell_updates = 0.0;
+
+    gfdtd_status prepare(const gfdtd_problem *probs, const int64_t *steps,
+                         int32_t count, const gfdtd_exec *ex, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+    void fill_desc(RunHost &r, const Group &G, int hl, int hr, int64_t own,
+                   int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd);
+    int live_tiles(const Group &G, int64_t b) const;
+    bool auto_graph() const;
+    gfdtd_status enqueue_zero(hipStream_t s);
+    gfdtd_status enqueue_steps(hipStream_t s);
+    gfdtd_status enqueue_dft(hipStream_t s);
+    gfdtd_status build_graphs();
+    gfdtd_status run();
+    gfdtd_status collect(gfdtd_result *outs);
+    void stats(gfdtd_stats *s) const;
+    ~Batch();
+};
+
+}  // namespace gfdtd

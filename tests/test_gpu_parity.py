@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Tolerances (relative L2 over each output):
+  FP64 path: 1e-12 -- the kernels use reciprocal coefficients and fused
+             multiply-adds, so they differ from the oracle only in rounding;
+  FP32 path: 1e-4  -- FP32 storage and stencil arithmetic; the measured
+             error is printed per case (typically 1e-7 .. 1e-5).
+Bit-for-bit on the GPU side: results do not depend on the tiling, the
+temporal block depth, graph capture or the batch they run in.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-4
+
+
+def rel(a, b):
+    den = np.linalg.norm(np.ravel(b))
+    num = np.linalg.norm(np.ravel(a) - np.ravel(b))
+    return float(num / den) if den > 0 else float(num)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2304_06586_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def compare(got, want, tol, label=""):
+    errs = {}
+    for key in ("trace", "dft", "d", "b"):
+        if key not in got or key not in want:
+            continue
+        a, b = got[key], want[key]
+        if key == "b":
+            a, b = a[:-1], b[:-1]
+        if np.size(b) == 0:
+            continue
+        errs[key] = rel(a, b)
+    print(f"{label}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+    assert got["status"] == 0
+    return errs
+
+
+def run(P, p, **exec_kw):
+    if not exec_kw:
+        return P.gfdtd_solve(p)
+    with P.Batch([p], **exec_kw) as b:
+        b.run()
+        return b.collect()[0]
+
+
+# ---------------------------------------------------------------------------
+
+def test_interface_config_fp64(P):
+    """Moving interface, 2000 cells x 4000 steps, FP64 (full size)."""
+    p = W.interface_run(0)
+    compare(run(P, p), oracle.solve(p), TOL64, "interface f64")
+
+
+def test_interface_config_fp32(P):
+    p = W.interface_run(0, precision=W.F32)
+    compare(run(P, p), oracle.solve(p), TOL32, "interface f32")
+
+
+CASES = [
+    # nz, steps, beta, kind, structure, abc
+    (8, 1, 0.3, W.MODULATION, "random", W.ABC_MUR1),
+    (9, 37, -0.2, W.MODULATION, "random", W.ABC_MUR1),
+    (63, 100, 0.45, W.MODULATION, "slab", W.ABC_MUR1),
+    (200, 333, 0.0, W.MODULATION, "random", W.ABC_MUR1),
+    (1000, 517, -0.35, W.MODULATION, "crystal", W.ABC_MUR1),
+    (3001, 1200, 0.3, W.MODULATION, "slab", W.ABC_PEC),
+    (4099, 900, 0.25, W.MATTER, "random", W.ABC_MUR1),
+    (2500, 700, -0.4, W.MATTER, "slab", W.ABC_MUR1),
+    (777, 64, 0.6, W.MODULATION, "uniform", W.ABC_PEC),
+]
+
+
+@pytest.mark.parametrize("nz,steps,beta,kind,structure,abc", CASES)
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_small_cases(P, nz, steps, beta, kind, structure, abc, precision):
+    p = W.small_case(nz, steps, beta, kind=kind, structure=structure, abc=abc,
+                     precision=precision, seed=nz + steps, nprobe=5)
+    want = oracle.solve(p)
+    tol = TOL64 if precision == W.F64 else TOL32
+    compare(run(P, p), want, tol, f"{nz}x{steps} b={beta} k={kind} p={precision}")
+
+
+@pytest.mark.parametrize("C,T", [(4, 1), (8, 1), (16, 1), (4, 7), (8, 16),
+                                 (16, 16), (16, 33), (8, 32), (4, 15)])
+@pytest.mark.parametrize("beta", [0.35, -0.3])
+def test_tilings_agree_bitwise_and_match_oracle(P, C, T, beta):
+    """Every (cells per lane, steps per launch) tiling gives the same bits,
+    and they match the oracle."""
+    p = W.small_case(2345, 301, beta, structure="crystal", seed=5, nprobe=5)
+    ref = run(P, p, cells_per_lane=8, block_steps=1, use_graph=0)
+    got = run(P, p, cells_per_lane=C, block_steps=T, use_graph=0)
+    for k in ("trace", "dft", "d", "b"):
+        assert np.array_equal(got[k], ref[k]), (C, T, k)
+    compare(got, oracle.solve(p), TOL64, f"C={C} T={T}")
+
+
+def test_graph_capture_matches_plain_launches(P):
+    p = W.small_case(1500, 800, 0.3, structure="slab", seed=9)
+    a = run(P, p, use_graph=0)
+    with P.Batch([p], use_graph=1) as b:
+        assert b.stats()["graph"] == 1
+        outs = []
+        for _ in range(3):              # replays, with host work between
+            b.run()
+            outs.append(b.collect()[0])
+    for o in outs:
+        for k in ("trace", "dft", "d", "b"):
+            assert np.array_equal(o[k], a[k]), k
+
+
+def test_batch_equals_alone_bitwise(P):
+    """Each run of a batch of mixed sizes, velocities, kinds and
+    precisions gives the same bits as the run alone."""
+    probs = [W.small_case(n, s, b, kind=k, precision=pr, structure=st, seed=i)
+             for i, (n, s, b, k, pr, st) in enumerate([
+                 (500, 200, 0.3, W.MODULATION, W.F64, "slab"),
+                 (3000, 900, -0.2, W.MODULATION, W.F64, "crystal"),
+                 (129, 1000, 0.5, W.MODULATION, W.F32, "random"),
+                 (2049, 17, 0.1, W.MATTER, W.F64, "random"),
+                 (900, 450, 0.4, W.MATTER, W.F32, "slab"),
+                 (64, 64, -0.45, W.MODULATION, W.F32, "uniform"),
+             ])]
+    batch = P.gfdtd_solve_batch(probs)
+    for p, got in zip(probs, batch):
+        alone = P.gfdtd_solve(p)
+        for k in ("trace", "dft", "d", "b"):
+            assert np.array_equal(got[k], alone[k]), (p.label, k)
+        tol = TOL64 if p.precision == W.F64 else TOL32
+        compare(got, oracle.solve(p), tol, p.label)
+
+
+def test_zero_steps_and_no_probes(P):
+    p = W.small_case(300, 0, 0.3, seed=2)
+    got = P.gfdtd_solve(p)
+    assert got["trace"].shape == (len(p.probes), 0)
+    assert np.all(got["d"] == 0) and np.all(got["dft"] == 0)
+    q = W.small_case(300, 50, 0.3, seed=2).replace(probes=np.zeros(0, np.int64),
+                                                   omegas=np.zeros(0))
+    got = P.gfdtd_solve(q)
+    want = oracle.solve(q)
+    assert rel(got["d"], want["d"]) < TOL64
+
+
+def test_probes_and_source_at_the_edges(P):
+    p = W.small_case(1111, 400, 0.3, seed=3, structure="random")
+    p = p.replace(src_cell=1, probes=np.array([0, 1, 2, 1108, 1109, 1110]))
+    compare(run(P, p), oracle.solve(p), TOL64, "edges src=1")
+    q = p.replace(src_cell=1109, beta=-0.3)
+    compare(run(P, q), oracle.solve(q), TOL64, "edges src=nz-2")
+
+
+# ---------------------------------------------------------------------------
+# Benchmark sizes, in the launch configuration the benchmark uses
+
+def test_slab_full_grid_first_steps_fp64(P):
+    """The 65536-cell moving slab at its full grid, stepped 3000 steps
+    (oracle-checkable), default tiling."""
+    p = W.slab_run(0).replace(steps=3000)
+    compare(run(P, p), oracle.solve(p), TOL64, "slab 65536x3000 f64")
+
+
+def test_gradient_downscaled_copy(P):
+    """Moving-matter tanh gradient, 2^14 cells x 2^12 steps: FP64 and
+    FP32 against the oracle."""
+    p = W.gradient_run(0, precision=W.F64, downscaled=True)
+    want = oracle.solve(p)
+    compare(run(P, p), want, TOL64, "gradient small f64")
+    compare(run(P, p.replace(precision=W.F32)), want, TOL32, "gradient small f32")
+
+
+def test_crystal_batch_sample(P):
+    """A seeded sample of the batched-crystal workload (first 8 runs,
+    steps cut to 4000 so the oracle finishes in seconds), batched."""
+    probs = [q.replace(steps=4000) for q in W.crystal_runs(0, count=8, precision=W.F64)]
+    got = P.gfdtd_solve_batch(probs)
+    for p, g in zip(probs, got):
+        compare(g, oracle.solve(p), TOL64, p.label)
