@@ -1,0 +1,262 @@
+"""Benchmark: batched generalized-FDTD solves on one MI355X.
+
+A "step" is one pass of the whole hot path over one batch: every run of the
+batched moving-bilayer-crystal workload (4096 runs, grid lengths
+log-uniform in [4096, 65536], 4 nz time steps each) stepped from zero
+fields to its last step, source, ends, probes and probe DFTs included.
+Inputs (rest profiles, probes, frequencies) are resident in HBM before the
+timed region.  `value` is total cell-updates (sum over runs of nz * steps)
+per second of the timed passes.
+
+Printed beside it, in the same JSON line:
+  plain       -- the plain single-run form: the 65536-cell moving slab,
+                 131072 steps, FP32 and FP64, one run per pass;
+  error       -- relative L2 error against the FP64 oracle on a seeded
+                 sample of the same workload;
+  roofline    -- the stepping kernel (k_tiles) against the chip's vector
+                 ALU peak, timed with HIP events on the library's stream;
+  cpu_baseline-- the oracle on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+METRIC = ("cell-updates/sec batched-served vs plain at fixed error; "
+          "p50/p99 solve latency")
+
+# Algorithmic arithmetic of one cell-update: eq. (10a)-(10d) with the
+# Table 1 terms as printed, one flop per add, subtract, multiply, divide:
+# (10a) 6, (10d) 5, (10b) 6, (10c) 5 for a moving modulation.
+FLOPS_PER_UPDATE = 22
+# Algorithmic HBM bytes of one cell-update: read and write D and B once.
+BYTES_PER_UPDATE = {W.F32: 16, W.F64: 32}
+# MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz, without packed FP32
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "k_tiles_f32_crystals4096_hbm_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic_per_update():
+    """HBM bytes per cell-update of k_tiles from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE counters (scaled by a plain copy), or None when
+    the kernel source has changed since they were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(COUNTERS):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def gpu_pass_rate(P, problems, passes, warmup, **exec_kw):
+    import torch
+    with P.Batch(problems, record_trace=False, fields=False, **exec_kw) as b:
+        for _ in range(warmup):
+            b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(passes):
+            b.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = b.stats()
+    return dt, st
+
+
+def cpu_baseline(sample, threads):
+    import oracle
+    t0 = time.perf_counter()
+    outs = oracle.solve_many(sample, threads=threads, fields=False)
+    dt = time.perf_counter() - t0
+    upd = sum(p.nz * p.steps for p in sample)
+    return upd / dt, dt, outs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--runs", type=int, default=4096)
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cells-per-lane", type=int, default=0)
+    ap.add_argument("--block-steps", type=int, default=0)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample-runs", type=int, default=64)
+    ap.add_argument("--cpu-sample-steps", type=int, default=6000)
+    ap.add_argument("--steps-cap", type=int, default=0, metavar="N",
+                    help="cap every run at N steps: a shorter workload with the "
+                         "same runs, tiles and launch shape, for counter "
+                         "collection (the reported value then covers it)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times), "
+                         "the reference for HBM byte counters")
+    args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "copies": 5}), flush=True)
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the "
+              "batched workload shards by runs with no communication, so the "
+              "per-GPU figure is the one reported.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2304_06586_amd as P
+    assert torch.cuda.is_available(), "no GPU"
+    P.load_library()
+    prec = W.F32 if args.precision == "f32" else W.F64
+    exec_kw = dict(cells_per_lane=args.cells_per_lane, block_steps=args.block_steps)
+
+    # ---------------------------------------------------------------- batched
+    log(f"generating {args.runs} crystal runs (seed {args.seed})")
+    probs = W.crystal_runs(args.seed, count=args.runs, precision=prec)
+    if args.steps_cap:
+        probs = [q.replace(steps=min(q.steps, args.steps_cap)) for q in probs]
+    updates = float(sum(p.nz * p.steps for p in probs))
+    log(f"cell-updates per pass: {updates:.4g}")
+    dt, st = gpu_pass_rate(P, probs, args.steps, args.warmup, **exec_kw)
+    value = updates * args.steps / dt
+    ms_per_step = dt * 1e3 / args.steps
+    log(f"batched: {value:.4g} cell-updates/s, {ms_per_step:.1f} ms per pass")
+
+    # roofline of the stepping kernel from the library's HIP events (last pass)
+    step_s = st["step_ms"] / 1e3
+    avg_launch_ms = st["step_ms"] / max(1, st["launches"])
+    k_rate = updates / step_s if step_s > 0 else 0.0
+    achieved_tflops = k_rate * FLOPS_PER_UPDATE / 1e12
+    hbm_equiv = k_rate * BYTES_PER_UPDATE[prec] / 1e9
+    per_update = measured_traffic_per_update() if prec == W.F32 else None
+    upd_per_launch = updates / max(1, st["launches"])
+    traffic = per_update * upd_per_launch if per_update is not None else None
+    roofline = {
+        "kernel": "k_tiles",
+        "bound": "alu",
+        "achieved": round(achieved_tflops, 3),
+        "peak": round(ALU_PEAK_TFLOPS, 1),
+        "unit": "TFLOP/s",
+        "frac": round(achieved_tflops / ALU_PEAK_TFLOPS, 4),
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                        "copy-calibrated)",
+        "measured_hbm_GBs": (round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
+                             if traffic is not None and avg_launch_ms > 0 else None),
+        "algorithmic_bytes_per_launch": upd_per_launch * BYTES_PER_UPDATE[prec],
+        "flops_per_update": FLOPS_PER_UPDATE,
+        "launches_per_pass": int(st["launches"]),
+        "avg_launch_ms": round(avg_launch_ms, 4),
+        "cells_per_lane": int(st["cells_per_lane"]),
+        "block_steps": int(st["block_steps"]),
+        "single_step_hbm_equiv_GBs": round(hbm_equiv, 1),
+        "single_step_hbm_frac": round(hbm_equiv / HBM_PEAK_GBS, 3),
+    }
+
+    # ------------------------------------------------------------------ plain
+    plain = None
+    if not args.no_plain:
+        plain = {}
+        for name, pr in (("f32", W.F32), ("f64", W.F64)):
+            p = W.slab_run(args.seed, precision=pr)
+            pdt, pst = gpu_pass_rate(P, [p], 1, 1)
+            plain[name] = {"value": p.nz * p.steps / pdt, "ms": pdt * 1e3,
+                           "cell_updates": p.nz * p.steps,
+                           "graph": int(pst["graph"])}
+            log(f"plain slab {name}: {plain[name]['value']:.4g} cell-updates/s")
+
+    # ---------------------------------------- error and CPU baseline (sample)
+    sample = [q.replace(steps=min(q.steps, args.cpu_sample_steps))
+              for q in W.crystal_runs(args.seed, count=args.cpu_sample_runs,
+                                      precision=prec)]
+    error = None
+    cpu = None
+    if not args.no_cpu:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"oracle on {len(sample)} runs x <= {args.cpu_sample_steps} steps, "
+            f"{threads} threads")
+        rate, cdt, ref = cpu_baseline(sample, threads)
+        got = P.gfdtd_solve_batch(sample, fields=False)
+        errs = []
+        for g, r in zip(got, ref):
+            num = np.linalg.norm(g["trace"] - r["trace"])
+            den = np.linalg.norm(r["trace"])
+            errs.append(num / den if den > 0 else num)
+        error = {"trace_rel_l2_max": float(max(errs)),
+                 "trace_rel_l2_median": float(np.median(errs)),
+                 "vs": "FP64 oracle", "sample": f"first {len(sample)} runs, "
+                 f"steps capped at {args.cpu_sample_steps}"}
+        cpu = {"value": rate, "unit": "cell-updates/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {len(sample)} runs of the same seeded batch, "
+                         f"each stepped min(4 nz, {args.cpu_sample_steps}) steps "
+                         f"({sum(p.nz * p.steps for p in sample):.3g} "
+                         f"cell-updates, {cdt:.1f} s)"}
+        log(f"cpu oracle: {rate:.4g} cell-updates/s on {threads} threads; "
+            f"gpu error max {error['trace_rel_l2_max']:.2e}")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched moving bilayer crystals, {args.runs} runs, "
+                        "nz log-uniform in [4096, 65536], steps = 4 nz, S = 0.5, "
+                        "lambda0 = 40 cells",
+            "runs": args.runs, "cell_updates_per_step": updates,
+            "steps_cap": args.steps_cap or None,
+            "seed": args.seed, "precision": args.precision,
+            "parallelism": "single GPU, all runs in one launch per time block",
+        },
+        "roofline": roofline,
+        "plain": plain,
+        "error": error,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -35,16 +35,43 @@ namespace gfdtd {
 
 // ------------------------------------------------------------ wave helpers
 
-template <typename R>
-__device__ __forceinline__ R from_left(R v)    // lane i <- lane i-1
+// Whole-wavefront shifts by one lane with DPP (wave_shr:1 / wave_shl:1):
+// one VALU move per 32-bit word, no LDS traffic.  The lane shifted in at
+// the wave edge reads 0.
+__device__ __forceinline__ int dpp_from_left(int v)
 {
-    return __shfl_up(v, 1, kWave);
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
 }
 
-template <typename R>
-__device__ __forceinline__ R from_right(R v)   // lane i <- lane i+1
+__device__ __forceinline__ int dpp_from_right(int v)
 {
-    return __shfl_down(v, 1, kWave);
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ float from_left(float v)     // lane i <- lane i-1
+{
+    return __int_as_float(dpp_from_left(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float from_right(float v)    // lane i <- lane i+1
+{
+    return __int_as_float(dpp_from_right(__float_as_int(v)));
+}
+
+__device__ __forceinline__ double from_left(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = dpp_from_left((int)(u & 0xffffffffLL));
+    const int hi = dpp_from_left((int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double from_right(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = dpp_from_right((int)(u & 0xffffffffLL));
+    const int hi = dpp_from_right((int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 template <typename R>
@@ -227,12 +254,14 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     const int64_t own_hi = x0 + W - (int64_t)hr * C;
 
     R Es[C], sums[C];
+    R Bup = (R)0;     // B of the cell just outside this lane, upwind side
 
     // E* of every cell from the current (D, B) and the E coefficients.
     auto compute_es = [&]() __attribute__((always_inline)) {
         if constexpr (!NEG) {
             const R Bm1 = from_left(B[C - 1]);
             const R Bm2 = from_left(B[C - 2]);
+            Bup = Bm1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const R b1 = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bm1;
@@ -241,6 +270,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         } else {
             const R Bp1 = from_right(B[0]);
+            Bup = Bp1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const R b1 = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bp1;
@@ -256,9 +286,15 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
     };
 
+    bool ownsProbe = false;
+    for (int q = 0; q < nprobe; ++q) {
+        const int64_t kp = rd->probes[q];
+        ownsProbe = ownsProbe || (kp >= own_lo && kp < own_hi);
+    }
+
     // Physical E = E* + beta Bbar at the owned probes, for time n-1/2.
     auto record = [&](int64_t n) __attribute__((always_inline)) {
-        if (n < 2)
+        if (n < 2 || !ownsProbe)
             return;
         for (int q = 0; q < nprobe; ++q) {
             const int64_t kp = rd->probes[q];
@@ -292,7 +328,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         const R DR = from_right(D[0]);
         R Bn[C], Hs[C];
         if constexpr (!NEG) {
-            const R Bm1 = from_left(B[C - 1]);
+            const R Bm1 = Bup;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
@@ -300,7 +336,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 Bn[c] = B[c] - S * (esn - Es[c]) - bS * (B[c] - bp);
             }
         } else {
-            const R Bp1 = from_right(B[0]);
+            const R Bp1 = Bup;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;

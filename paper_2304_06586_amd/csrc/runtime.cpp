@@ -255,18 +255,22 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 
 // --------------------------------------------------------------- tiling
 
+// Tiling defaults from measurements on MI355X: 8 cells per lane and 32
+// steps per launch for batches that fill the GPU; 4 cells per lane when the
+// group holds few cells (more, narrower tiles keep more SIMDs busy).
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
-                   int &C, int &T)
+                   int64_t total_cells, int &C, int &T)
 {
+    (void)precision;
     const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
     C = (ex && ex->cells_per_lane) ? ex->cells_per_lane
-                                   : (precision == GFDTD_F32 ? 16 : 8);
+                                   : (total_cells < (int64_t)4 << 20 ? 4 : 8);
     if (variant == GFDTD_VARIANT_STEP)
         T = 1;
     else if (ex && ex->block_steps > 0)
         T = ex->block_steps;
     else
-        T = 16;
+        T = 32;
     if (max_steps > 0 && T > max_steps)
         T = (int)std::max<int64_t>(1, max_steps);
 }
@@ -330,15 +334,16 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         Group G;
         G.precision = g >> 1;
         G.kind = g & 1;
-        int64_t max_steps = 0;
+        int64_t max_steps = 0, cells = 0;
         for (int i = 0; i < count; ++i)
             if (runs[i].p.precision == G.precision && runs[i].p.kind == G.kind) {
                 G.members.push_back(i);
                 max_steps = std::max(max_steps, runs[i].steps);
+                cells += runs[i].p.nz;
             }
         if (G.members.empty())
             continue;
-        choose_tiling(G.precision, ex, max_steps, G.C, G.T);
+        choose_tiling(G.precision, ex, max_steps, cells, G.C, G.T);
         for (int i : G.members)
             runs[i].T = G.T;
         int64_t maxt = 0;

@@ -40,7 +40,7 @@ void carve_run(Carver &cv, const gfdtd_problem *p, int64_t steps, RunLayout &L);
 size_t table_bytes(int nruns, int64_t max_tiles);
 int64_t max_tiles_of(int64_t nz);
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
-                   int &C, int &T);
+                   int64_t total_cells, int &C, int &T);
 bool halo_lanes(double beta, int C, int T, int &hl, int &hr);
 
 // A run with host copies of its inputs.

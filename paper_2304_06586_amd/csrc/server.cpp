@@ -134,8 +134,8 @@ struct Server {
         gfdtd_exec ex{};
         ex.struct_size = sizeof ex;
         ex.block_steps = cfg->block_steps;
-        choose_tiling(GFDTD_F32, &ex, 0, Cg[0], T);
-        choose_tiling(GFDTD_F64, &ex, 0, Cg[1], T);
+        choose_tiling(GFDTD_F32, &ex, 0, INT64_MAX, Cg[0], T);
+        choose_tiling(GFDTD_F64, &ex, 0, INT64_MAX, Cg[1], T);
         // descriptor tables at the front of the pool: run tables for every
         // slot and group, tile tables sized to the pool (a tile stores at
         // least 64 cells and a run costs more than 32 bytes per cell)
