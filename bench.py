@@ -87,6 +87,40 @@ def gpu_pass_rate(P, problems, passes, warmup, **exec_kw):
     return dt, st
 
 
+def serve(P, stream, pool_bytes, max_slots, blocks_per_call=64, closed=False):
+    """Drive the continuous-batching server with a request stream of
+    (arrival time, problem).  closed=True submits everything at t = 0
+    (saturation).  Returns (seconds from first arrival to last completion,
+    per-request latencies in s, total cell-updates)."""
+    lat = []
+    updates = 0
+    with P.Server(pool_bytes=pool_bytes, max_slots=max_slots) as srv:
+        pending = {}
+        i = 0
+        n = len(stream)
+        t0 = time.perf_counter()
+        while len(lat) < n:
+            now = time.perf_counter() - t0
+            while i < n and (closed or stream[i][0] <= now):
+                arr = 0.0 if closed else stream[i][0]
+                rid = srv.submit(stream[i][1])
+                pending[rid] = arr
+                updates += stream[i][1].nz * stream[i][1].steps
+                i += 1
+            if pending:
+                srv.progress(max_blocks=blocks_per_call)
+                for rid in list(pending):
+                    if srv.ready(rid):
+                        now = time.perf_counter() - t0
+                        r = srv.poll(rid)
+                        assert r["status"] == 0
+                        lat.append(now - pending.pop(rid))
+            elif i < n:
+                time.sleep(max(0.0, min(0.01, stream[i][0] - now)))
+        total = time.perf_counter() - t0
+    return total, lat, updates
+
+
 def cpu_baseline(sample, threads):
     import oracle
     t0 = time.perf_counter()
@@ -110,6 +144,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample-runs", type=int, default=64)
     ap.add_argument("--cpu-sample-steps", type=int, default=6000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-nz-hi", type=float, default=1e5)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the measured "
+                         "saturated request rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--steps-cap", type=int, default=0, metavar="N",
                     help="cap every run at N steps: a shorter workload with the "
                          "same runs, tiles and launch shape, for counter "
@@ -186,6 +228,48 @@ def main():
         "single_step_hbm_frac": round(hbm_equiv / HBM_PEAK_GBS, 3),
     }
 
+    # --------------------------------------------------- batched, other dtype
+    batched_f64 = None
+    if not args.no_f64 and prec == W.F32 and not args.steps_cap:
+        probs64 = [q.replace(precision=W.F64) for q in probs]
+        dt64, st64 = gpu_pass_rate(P, probs64, 1, 1, **exec_kw)
+        batched_f64 = {"value": updates / dt64, "ms": dt64 * 1e3,
+                       "cells_per_lane": int(st64["cells_per_lane"]),
+                       "block_steps": int(st64["block_steps"]),
+                       "hbm_equiv_frac": round(updates / dt64 * 32 / 8e12, 3)}
+        log(f"batched f64: {batched_f64['value']:.4g} cell-updates/s")
+        del probs64
+
+    # ---------------------------------------------------------------- served
+    serving = None
+    if not args.no_serve:
+        stream = W.serving_stream(args.seed, args.serve_requests, 1.0,
+                                  nz_hi=args.serve_nz_hi)
+        pool = int(args.serve_budget_gb * (1 << 30))
+        tot, lat, upd = serve(P, stream, pool, 512, closed=True)
+        cap = len(stream) / tot
+        rate = args.serve_load * cap
+        stream = W.serving_stream(args.seed, args.serve_requests, rate,
+                                  nz_hi=args.serve_nz_hi)
+        tot2, lat2, upd2 = serve(P, stream, pool, 512)
+        lat2 = np.array(lat2)
+        serving = {
+            "saturated_cell_updates_per_s": upd / tot,
+            "saturated_requests_per_s": cap,
+            "offered_requests_per_s": rate,
+            "cell_updates_per_s": upd2 / tot2,
+            "p50_latency_ms": float(np.percentile(lat2, 50) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat2, 99) * 1e3),
+            "requests": len(stream),
+            "mix": f"interface/slab/crystal/gradient, nz log-uniform in "
+                   f"[1e3, {args.serve_nz_hi:.0e}], steps U[2,4] nz, "
+                   "FP32 or FP64 with p = 1/2, Poisson arrivals",
+            "budget_GB": args.serve_budget_gb,
+        }
+        log(f"serving: saturated {serving['saturated_cell_updates_per_s']:.4g} "
+            f"cell-updates/s; at {rate:.1f} req/s p50 "
+            f"{serving['p50_latency_ms']:.1f} ms p99 {serving['p99_latency_ms']:.1f} ms")
+
     # ------------------------------------------------------------------ plain
     plain = None
     if not args.no_plain:
@@ -251,6 +335,8 @@ def main():
             "parallelism": "single GPU, all runs in one launch per time block",
         },
         "roofline": roofline,
+        "batched_f64": batched_f64,
+        "serving": serving,
         "plain": plain,
         "error": error,
         "cpu_baseline": cpu,

@@ -275,13 +275,17 @@ gfdtd_status gfdtd_server_create(const gfdtd_server_config *cfg,
  * the pool; GFDTD_E_INVALID / GFDTD_E_UNSTABLE as gfdtd_check. */
 gfdtd_status gfdtd_server_submit(gfdtd_server *s, const gfdtd_problem *p,
                                  int64_t steps, uint64_t *id);
-/* Run up to max_blocks progress blocks (admit, step, retire).  *live gets
- * the number of admitted runs afterwards, *queued the waiting ones (either
- * may be NULL). */
+/* Admit what fits, enqueue up to max_blocks progress blocks on the stream
+ * and retire the runs whose last block is enqueued (their DFT and result
+ * copies are enqueued too).  Returns without waiting for the GPU.  *live
+ * gets the number of admitted runs afterwards, *queued the waiting ones
+ * (either may be NULL). */
 gfdtd_status gfdtd_server_progress(gfdtd_server *s, int32_t max_blocks,
                                    int32_t *live, int32_t *queued);
-/* Copy a finished request's results (GFDTD_E_NOT_READY before).  A
- * request's results can be polled once; its record is then released. */
+/* GFDTD_E_NOT_READY until the request has finished.  With out == NULL,
+ * only reports readiness (GFDTD_OK once finished) and keeps the results;
+ * with a result struct, copies them and releases the request's record
+ * (results can be collected once). */
 gfdtd_status gfdtd_server_poll(gfdtd_server *s, uint64_t id, gfdtd_result *out);
 void gfdtd_server_destroy(gfdtd_server *s);
 

@@ -112,14 +112,36 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
 // the scheme in a uniform medium with eps' mu' = n2 (Section 5, App. A).
 // A plane wave D_k = D exp(i theta k), B_{k+1/2} = B exp(i theta (k+1/2))
 // is pushed through (10c), (10a), (10d), (10b) with the Table 1 terms.
-static double spectral_radius(double n2, double S, double beta, int kind,
-                              int ntheta)
+// The theta-dependent phase factors are computed once per scan.
+namespace {
+using cd = std::complex<double>;
+struct ThetaFactors {
+    cd curl, bbar, dlt, dbar;
+};
+
+std::vector<ThetaFactors> theta_factors(bool colA, int ntheta)
 {
-    using cd = std::complex<double>;
+    std::vector<ThetaFactors> f(ntheta);
+    for (int t = 1; t <= ntheta; ++t) {
+        const double th = M_PI * t / ntheta;
+        const cd h = std::polar(1.0, 0.5 * th);          // e^{i th/2}
+        const cd e1 = h * h;                             // e^{i th}
+        ThetaFactors &x = f[t - 1];
+        x.curl = h - 1.0 / h;
+        x.bbar = colA ? 0.5 * (1.0 / h + 1.0 / (h * e1)) : 0.5 * (h * e1 + h);
+        x.dlt = colA ? 1.0 - 1.0 / e1 : e1 - 1.0;
+        x.dbar = 0.5 * (h + 1.0 / h);
+    }
+    return f;
+}
+
+double spectral_radius(double n2, double S, double beta, int kind,
+                       const std::vector<ThetaFactors> &tf)
+{
     double aE, aH, bE, bH;
     if (kind == GFDTD_MATTER) {
         const double g = (1.0 - beta * beta) / (n2 - beta * beta);
-        aE = g;          // with mu' = 1 the product below only needs n2
+        aE = g;          // the eigenvalues depend on aE aH = g^2 n2 only
         aH = g * n2;
         bE = bH = g * beta;
     } else {
@@ -127,24 +149,16 @@ static double spectral_radius(double n2, double S, double beta, int kind,
         aH = 1.0;
         bE = bH = beta;
     }
-    const bool colA = beta >= 0.0;
     double best = 0.0;
-    for (int t = 1; t <= ntheta; ++t) {
-        const double th = M_PI * t / ntheta;
-        const cd h = std::polar(1.0, 0.5 * th);          // e^{i th/2}
-        const cd e1 = h * h;                             // e^{i th}
-        const cd curl = h - 1.0 / h;
-        const cd bbar = colA ? 0.5 * (1.0 / h + 1.0 / (h * e1)) : 0.5 * (h * e1 + h);
-        const cd dlt = colA ? 1.0 - 1.0 / e1 : e1 - 1.0;
-        const cd dbar = 0.5 * (h + 1.0 / h);
+    for (const ThetaFactors &x : tf) {
         cd G[2][2];
         for (int col = 0; col < 2; ++col) {
             const cd D = col == 0 ? 1.0 : 0.0;
             const cd B = col == 1 ? 1.0 : 0.0;
-            const cd Es = aE * D - bE * bbar * B;
-            const cd Bn = B - S * curl * Es - beta * S * dlt * B;
-            const cd Hs = aH * Bn - bH * dbar * D;
-            const cd Dn = D - S * curl * Hs - beta * S * dlt * D;
+            const cd Es = aE * D - bE * x.bbar * B;
+            const cd Bn = B - S * x.curl * Es - beta * S * x.dlt * B;
+            const cd Hs = aH * Bn - bH * x.dbar * D;
+            const cd Dn = D - S * x.curl * Hs - beta * S * x.dlt * D;
             G[0][col] = Dn;
             G[1][col] = Bn;
         }
@@ -156,11 +170,12 @@ static double spectral_radius(double n2, double S, double beta, int kind,
     }
     return best;
 }
+}  // namespace
 
 // The one-step matrix depends on the medium only through eps' mu' (for a
 // modulation through 1/(eps mu) and for matter through g), so distinct
-// products are scanned: all of them when few, else the extremes and 255
-// quantiles.
+// products are scanned: all of them when few, else the two extremes and
+// 30 quantiles between them.
 gfdtd_status preflight(const gfdtd_problem *p, double *growth)
 {
     std::vector<double> n2(p->nz);
@@ -169,15 +184,16 @@ gfdtd_status preflight(const gfdtd_problem *p, double *growth)
     std::sort(n2.begin(), n2.end());
     n2.erase(std::unique(n2.begin(), n2.end()), n2.end());
     std::vector<double> pick;
-    if (n2.size() <= 256) {
+    if (n2.size() <= 32) {
         pick = n2;
     } else {
-        for (int q = 0; q < 256; ++q)
-            pick.push_back(n2[(size_t)((n2.size() - 1) * (double)q / 255.0)]);
+        for (int q = 0; q < 32; ++q)
+            pick.push_back(n2[(size_t)((n2.size() - 1) * (double)q / 31.0)]);
     }
+    const std::vector<ThetaFactors> tf = theta_factors(p->beta >= 0.0, 512);
     double g = 0.0;
     for (double v : pick)
-        g = std::max(g, spectral_radius(v, p->courant, p->beta, p->kind, 512));
+        g = std::max(g, spectral_radius(v, p->courant, p->beta, p->kind, tf));
     if (growth)
         *growth = g;
     if (g > 1.0 + 1e-9 && !(p->flags & GFDTD_FLAG_ALLOW_UNSTABLE))

@@ -3,15 +3,30 @@
 // Requests wait in a FIFO queue until their device state fits in the pool
 // (the caller's HBM budget) and a slot is free.  Admitted runs share
 // progress blocks: one block advances every admitted run by T steps with
-// one k_tiles launch per (precision, kind) group.  The host knows each
-// run's last block in advance, so it enqueues blocks back to back up to the
-// next retirement, then waits once, forms the DFTs of the finished runs,
-// copies their results out, frees their memory and admits waiting
-// requests.  A run's arithmetic depends only on its own cells, so its
-// results are the same alone or in any mix.
+// one k_tiles launch per (precision, kind) group.
+//
+// Each (precision, kind) group runs on a stream of its own, so launches of
+// different groups overlap; they fork from the caller's stream at every
+// progress call.  Everything is stream-ordered, so the host never waits for
+// the GPU in steady state:
+//  - admission copies a request's inputs into a pinned host buffer, then
+//    asynchronously into its pool region (which also holds its own run,
+//    set-up and DFT descriptors), and enqueues its set-up and zero fill;
+//  - the run and tile tables of the live set are double-buffered in the
+//    pool and refreshed from pinned staging only when the set changes;
+//  - a run whose last block has been enqueued is retired at once: its DFT
+//    kernel and the copies of its results into its pinned buffer are
+//    enqueued and followed by an event; its pool region is released (any
+//    later use of that memory is ordered after those copies);
+//  - a run admitted into memory released by runs of other groups first
+//    waits for those runs' retirement events;
+//  - poll() checks the event.
+// A run's arithmetic depends only on its own cells and on its own start
+// block, so its results are the same bits alone or in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -28,7 +43,7 @@ namespace gfdtd {
 
 namespace {
 
-// First-fit allocator over [0, size) with coalescing free list.
+// First-fit allocator over [0, size) with a coalescing free list.
 struct Pool {
     size_t size = 0;
     std::map<size_t, size_t> free_;   // offset -> length
@@ -74,48 +89,146 @@ struct Pool {
     }
 };
 
-enum State { QUEUED, LIVE, DONE };
+// Pinned host memory owned by one request or staging slot.
+struct Pinned {
+    void *p = nullptr;
+    size_t n = 0;
+    ~Pinned()
+    {
+        if (p)
+            (void)hipHostFree(p);
+    }
+    hipError_t ensure(size_t bytes)
+    {
+        if (bytes <= n)
+            return hipSuccess;
+        if (p)
+            (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            n = bytes;
+        return e;
+    }
+};
+
+// Reusable pinned blocks in power-of-two size classes (pinning memory is
+// slow; requests come and go).
+struct PinnedPool {
+    std::map<size_t, std::vector<void *>> free_;
+    ~PinnedPool()
+    {
+        for (auto &kv : free_)
+            for (void *p : kv.second)
+                (void)hipHostFree(p);
+    }
+    static size_t klass(size_t n)
+    {
+        size_t k = 4096;
+        while (k < n)
+            k <<= 1;
+        return k;
+    }
+    hipError_t get(size_t n, void **p, size_t *cap)
+    {
+        const size_t k = klass(n);
+        auto &v = free_[k];
+        if (!v.empty()) {
+            *p = v.back();
+            v.pop_back();
+            *cap = k;
+            return hipSuccess;
+        }
+        *cap = k;
+        return hipHostMalloc(p, k, hipHostMallocDefault);
+    }
+    void put(void *p, size_t cap)
+    {
+        if (p)
+            free_[cap].push_back(p);
+    }
+};
+
+enum State { QUEUED, LIVE, RETIRING, DONE };
 
 struct Request {
     uint64_t id = 0;
     RunHost r;
     State state = QUEUED;
     size_t off = 0, bytes = 0;       // pool region
+    size_t desc_off = 0;             // RunDesc, PrepDesc, DftDesc of the run
     int group = 0;                   // precision * 2 + kind
     int hl = 0, hr = 0;
     int64_t own = 0, ntiles = 0;
     int64_t start_block = 0, end_block = 0;
-    // results
+    // pinned host block: inputs at admission, results at retirement
+    void *host = nullptr;
+    size_t host_cap = 0;
+    size_t h_dft = 0, h_trace = 0, h_d = 0, h_b = 0;
+    hipEvent_t done_ev = nullptr;
     int32_t status = GFDTD_OK;
-    std::vector<double> trace, dft_re, dft_im, final_d, final_b;
+    PinnedPool *pins = nullptr;
+    ~Request()
+    {
+        if (done_ev)
+            (void)hipEventDestroy(done_ev);
+        if (pins)
+            pins->put(host, host_cap);
+    }
 };
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
 struct Server {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;    // the caller's stream
+    hipStream_t gs[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr;
+    // per group: retirements (releases of pool memory) its stream has not
+    // yet been ordered after
+    std::vector<std::shared_ptr<void>> released[4];
+    PinnedPool pins;
     char *pool_base = nullptr;
     size_t pool_bytes = 0;
     int max_slots = 1;
-    int Cg[2] = {16, 8};             // cells per lane by precision
-    int T = 16;
+    int Cg[2] = {8, 8};              // cells per lane by precision
+    int T = 32;
     Pool pool;
-    size_t tables_off = 0, tables_bytes = 0;
+    size_t tables_bytes = 0;
     int64_t tile_cap = 0;
     uint64_t next_id = 1;
     int64_t gblock = 0;              // global block counter
     std::deque<uint64_t> queue;
     std::vector<uint64_t> live;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-    bool dirty = true;
-    // per group device tables (offsets in the pool)
-    size_t runs_off[4] = {0, 0, 0, 0}, tiles_off[4] = {0, 0, 0, 0};
-    size_t aux_off = 0;              // PrepDesc / DftDesc staging
+    bool gdirty[4] = {true, true, true, true};
+    int cur[4] = {0, 0, 0, 0};       // table buffer in use, per group
+    size_t runs_off[2][4], tiles_off[2][4];
     int ntiles[4] = {0, 0, 0, 0};
-    std::vector<RunDesc> h_rd[4];
-    std::vector<TileRef> h_tiles[4];
-    std::vector<PrepDesc> h_pd;
-    std::vector<DftDesc> h_dd;
+    Pinned stage[2][4];              // host staging of the table buffers
+    hipEvent_t stage_ev[2][4] = {};
+    bool stage_used[2][4] = {};
+
+    ~Server()
+    {
+        for (int g = 0; g < 4; ++g)
+            if (gs[g])
+                (void)hipStreamSynchronize(gs[g]);
+        reqs.clear();
+        for (auto &v : released)
+            v.clear();
+        for (auto &row : stage_ev)
+            for (auto &e : row)
+                if (e)
+                    (void)hipEventDestroy(e);
+        for (hipStream_t s : gs)
+            if (s)
+                (void)hipStreamDestroy(s);
+        if (fork_ev)
+            (void)hipEventDestroy(fork_ev);
+    }
 
     gfdtd_status create(const gfdtd_server_config *cfg)
     {
@@ -136,28 +249,41 @@ struct Server {
         ex.block_steps = cfg->block_steps;
         choose_tiling(GFDTD_F32, &ex, 0, INT64_MAX, Cg[0], T);
         choose_tiling(GFDTD_F64, &ex, 0, INT64_MAX, Cg[1], T);
-        // descriptor tables at the front of the pool: run tables for every
-        // slot and group, tile tables sized to the pool (a tile stores at
-        // least 64 cells and a run costs more than 32 bytes per cell)
+        // two copies of the run and tile tables at the front of the pool;
+        // a tile stores at least 64 cells and a run costs more than 32
+        // bytes per cell, which bounds the tiles the pool can hold
         tile_cap = (int64_t)(pool_bytes / (64 * 32)) + 8 * (int64_t)max_slots;
         Carver cv;
-        for (int g = 0; g < 4; ++g) {
-            runs_off[g] = cv.take((size_t)max_slots * sizeof(RunDesc));
-            tiles_off[g] = cv.take((size_t)tile_cap * sizeof(TileRef));
-        }
-        aux_off = cv.take((size_t)max_slots * std::max(sizeof(PrepDesc), sizeof(DftDesc)));
+        for (int k = 0; k < 2; ++k)
+            for (int g = 0; g < 4; ++g) {
+                runs_off[k][g] = cv.take((size_t)max_slots * sizeof(RunDesc));
+                tiles_off[k][g] = cv.take((size_t)tile_cap * sizeof(TileRef));
+            }
         tables_bytes = cv.off;
         if (tables_bytes >= pool_bytes)
             return fail(GFDTD_E_NOMEM, "pool of %zu bytes too small for the run tables "
                         "(%zu bytes)", pool_bytes, tables_bytes);
         pool.init(pool_bytes - tables_bytes);
+        hipError_t e;
+        for (int k = 0; k < 2; ++k)
+            for (int g = 0; g < 4; ++g)
+                if ((e = hipEventCreateWithFlags(&stage_ev[k][g], hipEventDisableTiming)))
+                    return hip_fail(e, "create events");
+        for (int g = 0; g < 4; ++g)
+            if ((e = hipStreamCreateWithFlags(&gs[g], hipStreamNonBlocking)))
+                return hip_fail(e, "create group streams");
+        if ((e = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming)))
+            return hip_fail(e, "create events");
         return GFDTD_OK;
     }
 
-    size_t footprint(const gfdtd_problem *p, int64_t steps, RunLayout &L) const
+    // Pool bytes of one request: its arrays plus its three descriptors.
+    size_t footprint(const gfdtd_problem *p, int64_t steps, RunLayout &L,
+                     size_t &desc_rel) const
     {
         Carver cv;
         carve_run(cv, p, steps, L);
+        desc_rel = cv.take(sizeof(RunDesc) + sizeof(PrepDesc) + sizeof(DftDesc));
         return cv.off;
     }
 
@@ -181,7 +307,7 @@ struct Server {
         r.p.mu_rest = r.mu.data();
         r.p.probe_cells = r.probes.data();
         r.p.omegas = r.omegas.data();
-        rq->bytes = footprint(&r.p, steps, r.L);
+        rq->bytes = footprint(&r.p, steps, r.L, rq->desc_off);
         if (rq->bytes > pool.size)
             return fail(GFDTD_E_NOMEM, "request needs %zu bytes, pool holds %zu",
                         rq->bytes, pool.size);
@@ -190,6 +316,9 @@ struct Server {
             return fail(GFDTD_E_INVALID, "block depth too large");
         rq->own = (int64_t)(kWave - rq->hl - rq->hr) * Cg[p->precision];
         rq->ntiles = (p->nz + rq->own - 1) / rq->own;
+        if (rq->ntiles > tile_cap)
+            return fail(GFDTD_E_NOMEM, "request needs %lld tiles, tables hold %lld",
+                        (long long)rq->ntiles, (long long)tile_cap);
         rq->id = next_id++;
         *id = rq->id;
         queue.push_back(rq->id);
@@ -200,7 +329,7 @@ struct Server {
     // Admit waiting requests in arrival order while they fit.
     gfdtd_status admit()
     {
-        std::vector<Request *> adm;
+        hipError_t e;
         while (!queue.empty() && (int)live.size() < max_slots) {
             Request *rq = reqs[queue.front()].get();
             if (ntiles[rq->group] + rq->ntiles > tile_cap)
@@ -210,161 +339,193 @@ struct Server {
                 break;
             queue.pop_front();
             rq->off = tables_bytes + off;
-            // offsets of the run's arrays relative to the pool base
             RunLayout &L = rq->r.L;
             size_t *fields[] = {&L.eps, &L.mu, &L.cE, &L.cH, &L.gB, &L.murL, &L.murR,
                                 &L.src, &L.probes, &L.omegas, &L.trace, &L.dft,
                                 &L.field[0], &L.field[1], &L.field[2], &L.field[3]};
             for (size_t *f : fields)
                 *f += rq->off;
+            rq->desc_off += rq->off;
             rq->state = LIVE;
             rq->start_block = gblock;
             rq->end_block = gblock + (rq->r.steps + T - 1) / T - 1;
             live.push_back(rq->id);
             ntiles[rq->group] += (int)rq->ntiles;
-            adm.push_back(rq);
-            dirty = true;
-        }
-        if (adm.empty())
-            return GFDTD_OK;
-        hipError_t e;
-        h_pd.resize(adm.size());
-        for (size_t i = 0; i < adm.size(); ++i) {
-            Request *rq = adm[i];
+            gdirty[rq->group] = true;
+            hipStream_t st = gs[rq->group];
+            // memory released by retirements on other streams is reused
+            // only after those retirements
+            for (auto &ev : released[rq->group])
+                if ((e = hipStreamWaitEvent(st, static_cast<hipEvent_t>(ev.get()), 0)))
+                    return hip_fail(e, "order memory reuse");
+            released[rq->group].clear();
+
+            // pinned buffer: inputs now, results at retirement
             RunHost &r = rq->r;
-            const size_t nz = (size_t)r.p.nz;
-            if ((e = hipMemcpyAsync(pool_base + r.L.eps, r.eps.data(), nz * 8,
-                                    hipMemcpyHostToDevice, stream)) ||
-                (e = hipMemcpyAsync(pool_base + r.L.mu, r.mu.data(), nz * 8,
-                                    hipMemcpyHostToDevice, stream)))
-                return hip_fail(e, "upload rest profile");
-            if (r.p.nprobe &&
-                (e = hipMemcpyAsync(pool_base + r.L.probes, r.probes.data(),
-                                    r.probes.size() * 8, hipMemcpyHostToDevice, stream)))
-                return hip_fail(e, "upload probes");
-            if (r.p.nfreq &&
-                (e = hipMemcpyAsync(pool_base + r.L.omegas, r.omegas.data(),
-                                    r.omegas.size() * 8, hipMemcpyHostToDevice, stream)))
-                return hip_fail(e, "upload omegas");
+            const gfdtd_problem &p = r.p;
+            const size_t nz = (size_t)p.nz;
+            const size_t w = p.precision == GFDTD_F32 ? 4 : 8;
+            size_t o = 0;
+            const size_t h_eps = o;  o += align256(nz * 8);
+            const size_t h_mu = o;   o += align256(nz * 8);
+            const size_t h_pr = o;   o += align256(std::max<size_t>(r.probes.size(), 1) * 8);
+            const size_t h_om = o;   o += align256(std::max<size_t>(r.omegas.size(), 1) * 8);
+            const size_t h_desc = o; o += align256(sizeof(RunDesc) + sizeof(PrepDesc) +
+                                                   sizeof(DftDesc));
+            rq->h_dft = o;   o += align256((size_t)std::max(p.nprobe * p.nfreq, 1) * 16);
+            rq->h_trace = o;
+            if (p.flags & GFDTD_FLAG_RECORD_TRACE)
+                o += align256((size_t)std::max<int64_t>((int64_t)p.nprobe * r.steps, 1) * 8);
+            rq->h_d = o;
+            rq->h_b = o;
+            if (p.flags & GFDTD_FLAG_KEEP_FIELDS) {
+                o += align256(nz * w);
+                rq->h_b = o;
+                o += align256(nz * w);
+            }
+            if ((e = pins.get(o, &rq->host, &rq->host_cap)))
+                return hip_fail(e, "pinned host buffer");
+            rq->pins = &pins;
+            char *h = static_cast<char *>(rq->host);
+            std::memcpy(h + h_eps, r.eps.data(), nz * 8);
+            std::memcpy(h + h_mu, r.mu.data(), nz * 8);
+            if (!r.probes.empty())
+                std::memcpy(h + h_pr, r.probes.data(), r.probes.size() * 8);
+            if (!r.omegas.empty())
+                std::memcpy(h + h_om, r.omegas.data(), r.omegas.size() * 8);
             RunDesc rd;
+            PrepDesc pd;
             DftDesc dd;
-            fill_run_desc(pool_base, r, r.p.precision, rq->hl, rq->hr, rq->own,
-                          rq->start_block, rd, h_pd[i], dd);
-        }
-        // set-up and zero fill, grouped by precision (word size)
-        for (int prec = 0; prec < 2; ++prec) {
-            std::vector<PrepDesc> sel;
-            int64_t maxc = 0, maxf = 0;
-            for (size_t i = 0; i < adm.size(); ++i)
-                if (adm[i]->r.p.precision == prec) {
-                    sel.push_back(h_pd[i]);
-                    maxc = std::max<int64_t>(maxc, std::max(adm[i]->r.p.nz, adm[i]->r.L.nsrc));
-                    maxf = std::max<int64_t>(maxf, field_cells(adm[i]->r.p.nz));
-                }
-            if (sel.empty())
-                continue;
-            if ((e = hipMemcpyAsync(pool_base + aux_off, sel.data(),
-                                    sel.size() * sizeof(PrepDesc), hipMemcpyHostToDevice,
-                                    stream)))
-                return hip_fail(e, "upload set-up table");
-            const PrepDesc *dp = reinterpret_cast<const PrepDesc *>(pool_base + aux_off);
-            if ((e = launch_prep(dp, (int)sel.size(), (int)std::min<int64_t>(maxc, 1 << 30),
-                                 stream)) ||
-                (e = launch_zero(dp, (int)sel.size(), maxf, prec, stream)))
+            fill_run_desc(pool_base, r, p.precision, rq->hl, rq->hr, rq->own,
+                          rq->start_block, rd, pd, dd);
+            std::memcpy(h + h_desc, &rd, sizeof rd);
+            std::memcpy(h + h_desc + sizeof rd, &pd, sizeof pd);
+            std::memcpy(h + h_desc + sizeof rd + sizeof pd, &dd, sizeof dd);
+            const size_t desc_bytes = sizeof rd + sizeof pd + sizeof dd;
+            if ((e = hipMemcpyAsync(pool_base + L.eps, h + h_eps, nz * 8,
+                                    hipMemcpyHostToDevice, st)) ||
+                (e = hipMemcpyAsync(pool_base + L.mu, h + h_mu, nz * 8,
+                                    hipMemcpyHostToDevice, st)) ||
+                (e = hipMemcpyAsync(pool_base + rq->desc_off, h + h_desc, desc_bytes,
+                                    hipMemcpyHostToDevice, st)))
+                return hip_fail(e, "upload request");
+            if (!r.probes.empty() &&
+                (e = hipMemcpyAsync(pool_base + L.probes, h + h_pr, r.probes.size() * 8,
+                                    hipMemcpyHostToDevice, st)))
+                return hip_fail(e, "upload probes");
+            if (!r.omegas.empty() &&
+                (e = hipMemcpyAsync(pool_base + L.omegas, h + h_om, r.omegas.size() * 8,
+                                    hipMemcpyHostToDevice, st)))
+                return hip_fail(e, "upload omegas");
+            const PrepDesc *dp =
+                reinterpret_cast<const PrepDesc *>(pool_base + rq->desc_off + sizeof(RunDesc));
+            if ((e = launch_prep(dp, 1, (int)std::min<int64_t>(std::max(p.nz, L.nsrc), 1 << 30),
+                                 st)) ||
+                (e = launch_zero(dp, 1, field_cells(p.nz), p.precision, st)))
                 return hip_fail(e, "launch set-up");
-            // the staging table is reused: finish before the next upload
-            if ((e = hipStreamSynchronize(stream)))
-                return hip_fail(e, "set-up");
         }
         return GFDTD_OK;
     }
 
-    gfdtd_status rebuild_tables()
+    // Write a group's tables into its spare buffer (stream-ordered after
+    // every launch that used it) and switch to it.
+    gfdtd_status rebuild_tables(int g)
     {
         hipError_t e;
-        for (int g = 0; g < 4; ++g) {
-            h_rd[g].clear();
-            h_tiles[g].clear();
-        }
+        const int nxt = cur[g] ^ 1;
+        std::vector<RunDesc> rd;
+        std::vector<TileRef> tl;
         for (uint64_t id : live) {
             Request *rq = reqs[id].get();
-            const int g = rq->group;
-            RunDesc rd;
+            if (rq->group != g)
+                continue;
+            RunDesc d;
             PrepDesc pd;
             DftDesc dd;
             fill_run_desc(pool_base, rq->r, rq->r.p.precision, rq->hl, rq->hr, rq->own,
-                          rq->start_block, rd, pd, dd);
-            const int m = (int)h_rd[g].size();
-            h_rd[g].push_back(rd);
+                          rq->start_block, d, pd, dd);
+            const int m = (int)rd.size();
+            rd.push_back(d);
             for (int64_t t = 0; t < rq->ntiles; ++t)
-                h_tiles[g].push_back(TileRef{m, (int32_t)t});
+                tl.push_back(TileRef{m, (int32_t)t});
         }
-        for (int g = 0; g < 4; ++g) {
-            ntiles[g] = (int)h_tiles[g].size();
-            if (h_rd[g].empty())
-                continue;
-            if ((e = hipMemcpyAsync(pool_base + runs_off[g], h_rd[g].data(),
-                                    h_rd[g].size() * sizeof(RunDesc),
-                                    hipMemcpyHostToDevice, stream)) ||
-                (e = hipMemcpyAsync(pool_base + tiles_off[g], h_tiles[g].data(),
-                                    h_tiles[g].size() * sizeof(TileRef),
-                                    hipMemcpyHostToDevice, stream)))
-                return hip_fail(e, "upload run tables");
-        }
-        dirty = false;
+        ntiles[g] = (int)tl.size();
+        gdirty[g] = false;
+        cur[g] = nxt;
+        if (rd.empty())
+            return GFDTD_OK;
+        const size_t a = rd.size() * sizeof(RunDesc);
+        const size_t b = tl.size() * sizeof(TileRef);
+        // the staging buffer's previous copies must have been consumed
+        if (stage_used[nxt][g] && (e = hipEventSynchronize(stage_ev[nxt][g])))
+            return hip_fail(e, "table staging");
+        if ((e = stage[nxt][g].ensure(align256(a) + align256(b))))
+            return hip_fail(e, "pinned table staging");
+        char *h = static_cast<char *>(stage[nxt][g].p);
+        std::memcpy(h, rd.data(), a);
+        std::memcpy(h + align256(a), tl.data(), b);
+        if ((e = hipMemcpyAsync(pool_base + runs_off[nxt][g], h, a, hipMemcpyHostToDevice,
+                                gs[g])) ||
+            (e = hipMemcpyAsync(pool_base + tiles_off[nxt][g], h + align256(a), b,
+                                hipMemcpyHostToDevice, gs[g])) ||
+            (e = hipEventRecord(stage_ev[nxt][g], gs[g])))
+            return hip_fail(e, "upload tables");
+        stage_used[nxt][g] = true;
         return GFDTD_OK;
     }
 
-    gfdtd_status retire(const std::vector<Request *> &done)
+    // Enqueue the DFT and result copies of a run whose last block has been
+    // enqueued, release its pool region and drop it from the live set.
+    gfdtd_status retire(Request *rq)
     {
         hipError_t e;
-        h_dd.resize(done.size());
-        for (size_t i = 0; i < done.size(); ++i) {
-            RunDesc rd;
-            PrepDesc pd;
-            fill_run_desc(pool_base, done[i]->r, done[i]->r.p.precision, done[i]->hl,
-                          done[i]->hr, done[i]->own, done[i]->start_block, rd, pd,
-                          h_dd[i]);
+        const gfdtd_problem &p = rq->r.p;
+        const RunLayout &L = rq->r.L;
+        char *h = static_cast<char *>(rq->host);
+        hipStream_t stream = gs[rq->group];
+        const DftDesc *dd = reinterpret_cast<const DftDesc *>(
+            pool_base + rq->desc_off + sizeof(RunDesc) + sizeof(PrepDesc));
+        if ((e = launch_dft(dd, 1, p.nprobe * p.nfreq, stream)))
+            return hip_fail(e, "launch DFT");
+        if (p.nprobe * p.nfreq > 0 &&
+            (e = hipMemcpyAsync(h + rq->h_dft, pool_base + L.dft,
+                                (size_t)p.nprobe * p.nfreq * 16, hipMemcpyDeviceToHost,
+                                stream)))
+            return hip_fail(e, "copy DFT");
+        if ((p.flags & GFDTD_FLAG_RECORD_TRACE) && p.nprobe > 0 && rq->r.steps > 0 &&
+            (e = hipMemcpyAsync(h + rq->h_trace, pool_base + L.trace,
+                                (size_t)p.nprobe * rq->r.steps * 8, hipMemcpyDeviceToHost,
+                                stream)))
+            return hip_fail(e, "copy trace");
+        if ((p.flags & GFDTD_FLAG_KEEP_FIELDS) && rq->r.steps > 0) {
+            const size_t w = p.precision == GFDTD_F32 ? 4 : 8;
+            const int fin = (int)(((rq->r.steps + T - 1) / T) & 1);
+            if ((e = hipMemcpyAsync(h + rq->h_d, pool_base + L.field[fin] + kPad * w,
+                                    (size_t)p.nz * w, hipMemcpyDeviceToHost, stream)) ||
+                (e = hipMemcpyAsync(h + rq->h_b, pool_base + L.field[2 + fin] + kPad * w,
+                                    (size_t)p.nz * w, hipMemcpyDeviceToHost, stream)))
+                return hip_fail(e, "copy fields");
         }
-        int max_pf = 0;
-        for (auto *rq : done)
-            max_pf = std::max(max_pf, rq->r.p.nprobe * rq->r.p.nfreq);
-        if (!done.empty()) {
-            if ((e = hipMemcpyAsync(pool_base + aux_off, h_dd.data(),
-                                    h_dd.size() * sizeof(DftDesc), hipMemcpyHostToDevice,
-                                    stream)))
-                return hip_fail(e, "upload DFT table");
-            if ((e = launch_dft(reinterpret_cast<const DftDesc *>(pool_base + aux_off),
-                                (int)done.size(), max_pf, stream)))
-                return hip_fail(e, "launch DFT");
-        }
-        for (auto *rq : done) {
-            const gfdtd_problem &p = rq->r.p;
-            rq->dft_re.assign((size_t)p.nprobe * p.nfreq, 0.0);
-            rq->dft_im.assign((size_t)p.nprobe * p.nfreq, 0.0);
-            if (p.flags & GFDTD_FLAG_RECORD_TRACE)
-                rq->trace.assign((size_t)p.nprobe * rq->r.steps, 0.0);
-            if (p.flags & GFDTD_FLAG_KEEP_FIELDS) {
-                rq->final_d.assign((size_t)p.nz, 0.0);
-                rq->final_b.assign((size_t)p.nz, 0.0);
-            }
-            gfdtd_result out{};
-            out.struct_size = sizeof out;
-            out.trace = rq->trace.empty() ? nullptr : rq->trace.data();
-            out.dft_re = rq->dft_re.data();
-            out.dft_im = rq->dft_im.data();
-            out.final_d = rq->final_d.empty() ? nullptr : rq->final_d.data();
-            out.final_b = rq->final_b.empty() ? nullptr : rq->final_b.data();
-            gfdtd_status st = copy_results(pool_base, rq->r, nullptr, stream, &out);
-            if (st != GFDTD_OK)
-                return st;
-            rq->status = out.run_status;
-            rq->state = DONE;
-            pool.release(rq->off - tables_bytes, rq->bytes);
-            ntiles[rq->group] -= (int)rq->ntiles;
-            live.erase(std::find(live.begin(), live.end(), rq->id));
-            dirty = true;
-        }
+        if ((e = hipEventCreateWithFlags(&rq->done_ev, hipEventDisableTiming)) ||
+            (e = hipEventRecord(rq->done_ev, stream)))
+            return hip_fail(e, "record retirement");
+        // a server-owned event orders later reuse of the region on other
+        // streams (the request's own event lives only until it is polled)
+        hipEvent_t rel = nullptr;
+        if ((e = hipEventCreateWithFlags(&rel, hipEventDisableTiming)) ||
+            (e = hipEventRecord(rel, stream)))
+            return hip_fail(e, "record release");
+        std::shared_ptr<void> ev(rel, [](void *x) {
+            (void)hipEventDestroy(static_cast<hipEvent_t>(x));
+        });
+        for (int g = 0; g < 4; ++g)
+            if (g != rq->group)
+                released[g].push_back(ev);
+        rq->state = RETIRING;
+        pool.release(rq->off - tables_bytes, rq->bytes);
+        ntiles[rq->group] -= (int)rq->ntiles;
+        live.erase(std::find(live.begin(), live.end(), rq->id));
+        gdirty[rq->group] = true;
         return GFDTD_OK;
     }
 
@@ -373,23 +534,33 @@ struct Server {
         hipError_t e;
         int32_t left = max_blocks < 0 ? 0 : max_blocks;
         gfdtd_status st;
-        // zero-step requests finish on admission
-        while (left > 0) {
+        // order the server's work after what the caller has enqueued
+        if ((e = hipEventRecord(fork_ev, stream)))
+            return hip_fail(e, "fork");
+        for (hipStream_t g : gs)
+            if ((e = hipStreamWaitEvent(g, fork_ev, 0)))
+                return hip_fail(e, "fork");
+        while (true) {
             if ((st = admit()) != GFDTD_OK)
                 return st;
-            std::vector<Request *> done;
-            for (uint64_t id : live)
-                if (reqs[id]->r.steps == 0)
-                    done.push_back(reqs[id].get());
-            if (!done.empty()) {
-                if ((st = retire(done)) != GFDTD_OK)
-                    return st;
-                continue;
+            bool retired = false;
+            for (size_t i = 0; i < live.size();) {
+                Request *rq = reqs[live[i]].get();
+                if (rq->r.steps == 0) {      // nothing to step
+                    if ((st = retire(rq)) != GFDTD_OK)
+                        return st;
+                    retired = true;
+                } else {
+                    ++i;
+                }
             }
-            if (live.empty())
+            if (retired)
+                continue;
+            if (live.empty() || left <= 0)
                 break;
-            if (dirty && (st = rebuild_tables()) != GFDTD_OK)
-                return st;
+            for (int g = 0; g < 4; ++g)
+                if (gdirty[g] && (st = rebuild_tables(g)) != GFDTD_OK)
+                    return st;
             int64_t next_end = INT64_MAX;
             for (uint64_t id : live)
                 next_end = std::min(next_end, reqs[id]->end_block);
@@ -399,21 +570,23 @@ struct Server {
                     if (!ntiles[g])
                         continue;
                     e = launch_tiles(g >> 1, g & 1, Cg[g >> 1],
-                                     reinterpret_cast<const RunDesc *>(pool_base + runs_off[g]),
-                                     reinterpret_cast<const TileRef *>(pool_base + tiles_off[g]),
-                                     gblock, T, ntiles[g], stream);
+                                     reinterpret_cast<const RunDesc *>(pool_base + runs_off[cur[g]][g]),
+                                     reinterpret_cast<const TileRef *>(pool_base + tiles_off[cur[g]][g]),
+                                     gblock, T, ntiles[g], gs[g]);
                     if (e)
                         return hip_fail(e, "launch step kernel");
                 }
             left -= (int32_t)nb;
-            for (uint64_t id : live)
-                if (reqs[id]->end_block < gblock)
-                    done.push_back(reqs[id].get());
-            if (!done.empty() && (st = retire(done)) != GFDTD_OK)
-                return st;
+            for (size_t i = 0; i < live.size();) {
+                Request *rq = reqs[live[i]].get();
+                if (rq->end_block < gblock) {
+                    if ((st = retire(rq)) != GFDTD_OK)
+                        return st;
+                } else {
+                    ++i;
+                }
+            }
         }
-        if ((e = hipStreamSynchronize(stream)))
-            return hip_fail(e, "progress");
         if (nlive)
             *nlive = (int32_t)live.size();
         if (nqueued)
@@ -427,22 +600,58 @@ struct Server {
         if (it == reqs.end())
             return fail(GFDTD_E_INVALID, "unknown request %llu", (unsigned long long)id);
         Request *rq = it->second.get();
-        if (rq->state != DONE)
+        if (rq->state == QUEUED || rq->state == LIVE)
             return GFDTD_E_NOT_READY;
-        if (!out || out->struct_size < sizeof(gfdtd_result))
+        if (rq->state == RETIRING) {
+            hipError_t q = hipEventQuery(rq->done_ev);
+            if (q == hipErrorNotReady)
+                return GFDTD_E_NOT_READY;
+            if (q != hipSuccess)
+                return hip_fail(q, "retirement");
+            rq->state = DONE;
+            const gfdtd_problem &p = rq->r.p;
+            const char *h = static_cast<const char *>(rq->host);
+            bool finite = true;
+            const double *dft = reinterpret_cast<const double *>(h + rq->h_dft);
+            for (int i = 0; i < 2 * p.nprobe * p.nfreq; ++i)
+                finite = finite && std::isfinite(dft[i]);
+            if (p.flags & GFDTD_FLAG_RECORD_TRACE) {
+                const double *tr = reinterpret_cast<const double *>(h + rq->h_trace);
+                for (int64_t i = 0; i < (int64_t)p.nprobe * rq->r.steps; ++i)
+                    finite = finite && std::isfinite(tr[i]);
+            }
+            rq->status = finite ? GFDTD_OK : GFDTD_E_BLOWUP;
+        }
+        if (!out)                    // readiness query only
+            return GFDTD_OK;
+        if (out->struct_size < sizeof(gfdtd_result))
             return fail(GFDTD_E_INVALID, "bad result struct");
+        const gfdtd_problem &p = rq->r.p;
+        const char *h = static_cast<const char *>(rq->host);
         out->run_status = rq->status;
         out->steps_done = rq->r.steps;
-        if (out->dft_re && out->dft_im && !rq->dft_re.empty()) {
-            std::memcpy(out->dft_re, rq->dft_re.data(), rq->dft_re.size() * 8);
-            std::memcpy(out->dft_im, rq->dft_im.data(), rq->dft_im.size() * 8);
+        const double *dft = reinterpret_cast<const double *>(h + rq->h_dft);
+        if (out->dft_re && out->dft_im)
+            for (int i = 0; i < p.nprobe * p.nfreq; ++i) {
+                out->dft_re[i] = dft[2 * i];
+                out->dft_im[i] = dft[2 * i + 1];
+            }
+        if (out->trace && (p.flags & GFDTD_FLAG_RECORD_TRACE) && p.nprobe > 0)
+            std::memcpy(out->trace, h + rq->h_trace, (size_t)p.nprobe * rq->r.steps * 8);
+        const bool keep = (p.flags & GFDTD_FLAG_KEEP_FIELDS) != 0;
+        const bool f32 = p.precision == GFDTD_F32;
+        auto field = [&](size_t o, double *dst, int64_t n) {
+            for (int64_t i = 0; i < n; ++i)
+                dst[i] = rq->r.steps == 0 ? 0.0
+                         : f32 ? (double)reinterpret_cast<const float *>(h + o)[i]
+                               : reinterpret_cast<const double *>(h + o)[i];
+        };
+        if (out->final_d && keep)
+            field(rq->h_d, out->final_d, p.nz);
+        if (out->final_b && keep) {
+            field(rq->h_b, out->final_b, p.nz - 1);
+            out->final_b[p.nz - 1] = 0.0;
         }
-        if (out->trace && !rq->trace.empty())
-            std::memcpy(out->trace, rq->trace.data(), rq->trace.size() * 8);
-        if (out->final_d && !rq->final_d.empty())
-            std::memcpy(out->final_d, rq->final_d.data(), rq->final_d.size() * 8);
-        if (out->final_b && !rq->final_b.empty())
-            std::memcpy(out->final_b, rq->final_b.data(), rq->final_b.size() * 8);
         reqs.erase(it);
         return GFDTD_OK;
     }
@@ -498,8 +707,7 @@ void gfdtd_server_destroy(gfdtd_server *s)
 {
     if (s) {
         Server *sv = reinterpret_cast<Server *>(s);
-        (void)hipStreamSynchronize(sv->stream);
-        delete sv;
+        delete sv;      // waits for the group streams
     }
 }
 

@@ -209,8 +209,8 @@ class _Marshalled:
 class _ResultBuffers:
     """Host buffers for one gfdtd_result."""
 
-    def __init__(self, m: _Marshalled, fields: bool = True):
-        self.trace = np.zeros((m.nprobe, m.steps))
+    def __init__(self, m: _Marshalled, fields: bool = True, trace: bool = True):
+        self.trace = np.zeros((m.nprobe, m.steps if trace else 0))
         self.dre = np.zeros((m.nprobe, m.nfreq))
         self.dim = np.zeros((m.nprobe, m.nfreq))
         self.d = np.zeros(m.nz) if fields else None
@@ -443,14 +443,22 @@ class Server:
                                                C.byref(live), C.byref(queued)))
         return live.value, queued.value
 
+    def ready(self, rid: int) -> bool:
+        st = self._lib.gfdtd_server_poll(self._h, C.c_uint64(rid), None)
+        if st == GFDTD_E_NOT_READY:
+            return False
+        _check(st)
+        return True
+
     def poll(self, rid: int) -> Optional[Dict[str, np.ndarray]]:
+        """Results of a finished request (collected once), else None."""
+        if not self.ready(rid):
+            return None
         m = self._pending[rid]
         fields = bool(m.struct.flags & GFDTD_FLAG_KEEP_FIELDS)
-        out = _ResultBuffers(m, fields)
-        st = self._lib.gfdtd_server_poll(self._h, C.c_uint64(rid), C.byref(out.struct))
-        if st == GFDTD_E_NOT_READY:
-            return None
-        _check(st)
+        trace = bool(m.struct.flags & GFDTD_FLAG_RECORD_TRACE)
+        out = _ResultBuffers(m, fields, trace)
+        _check(self._lib.gfdtd_server_poll(self._h, C.c_uint64(rid), C.byref(out.struct)))
         del self._pending[rid]
         return out.as_dict()
 

@@ -110,9 +110,11 @@ def test_poll_not_ready_and_budget_errors(P):
 
 def test_zero_step_request(P):
     p = W.small_case(500, 0, 0.2, seed=6)
+    import torch
     with P.Server(pool_bytes=64 << 20, max_slots=2) as srv:
         rid = srv.submit(p, record_trace=True, keep_fields=True)
         srv.progress(max_blocks=1)
+        torch.cuda.synchronize()        # progress returns without waiting
         r = srv.poll(rid)
         assert r is not None and r["steps_done"] == 0
         assert np.all(r["d"] == 0)
