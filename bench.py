@@ -53,10 +53,11 @@ COUNTERS = os.path.join(ROOT, "profiles", "k_tiles_f32_crystals4096_hbm_counters
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic_per_update():
+def measured_traffic_per_update(C, T):
     """HBM bytes per cell-update of k_tiles from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE counters (scaled by a plain copy), or None when
-    the kernel source has changed since they were taken."""
+    the kernel source has changed since they were taken or they were taken
+    at another tiling (cells per lane C, steps per launch T)."""
     import hashlib
     try:
         kv = {}
@@ -67,14 +68,18 @@ def measured_traffic_per_update():
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         if kv.get("kernel_source_sha256") != sha:
             return None
+        if int(kv["cells_per_lane"]) != C or int(kv["block_steps"]) != T:
+            return None
         return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def gpu_pass_rate(P, problems, passes, warmup, **exec_kw):
+def gpu_pass_rate(P, problems, passes, warmup, tune=True, **exec_kw):
     import torch
     with P.Batch(problems, record_trace=False, fields=False, **exec_kw) as b:
+        if tune:                      # outside the timed region
+            b.autotune(trial_blocks=4)
         for _ in range(warmup):
             b.run()
         torch.cuda.synchronize()
@@ -145,6 +150,8 @@ def main():
     ap.add_argument("--cpu-sample-runs", type=int, default=64)
     ap.add_argument("--cpu-sample-steps", type=int, default=6000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tiling instead of autotuning it")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-nz-hi", type=float, default=1e5)
@@ -183,7 +190,9 @@ def main():
     assert torch.cuda.is_available(), "no GPU"
     P.load_library()
     prec = W.F32 if args.precision == "f32" else W.F64
-    exec_kw = dict(cells_per_lane=args.cells_per_lane, block_steps=args.block_steps)
+    exec_kw = dict(cells_per_lane=args.cells_per_lane, block_steps=args.block_steps,
+                   tune=not args.no_tune and not args.cells_per_lane
+                   and not args.block_steps)
 
     # ---------------------------------------------------------------- batched
     log(f"generating {args.runs} crystal runs (seed {args.seed})")
@@ -203,7 +212,9 @@ def main():
     k_rate = updates / step_s if step_s > 0 else 0.0
     achieved_tflops = k_rate * FLOPS_PER_UPDATE / 1e12
     hbm_equiv = k_rate * BYTES_PER_UPDATE[prec] / 1e9
-    per_update = measured_traffic_per_update() if prec == W.F32 else None
+    per_update = (measured_traffic_per_update(int(st["cells_per_lane"]),
+                                              int(st["block_steps"]))
+                  if prec == W.F32 else None)
     upd_per_launch = updates / max(1, st["launches"])
     traffic = per_update * upd_per_launch if per_update is not None else None
     roofline = {
@@ -274,13 +285,20 @@ def main():
     plain = None
     if not args.no_plain:
         plain = {}
-        for name, pr in (("f32", W.F32), ("f64", W.F64)):
-            p = W.slab_run(args.seed, precision=pr)
-            pdt, pst = gpu_pass_rate(P, [p], 1, 1)
-            plain[name] = {"value": p.nz * p.steps / pdt, "ms": pdt * 1e3,
-                           "cell_updates": p.nz * p.steps,
-                           "graph": int(pst["graph"])}
-            log(f"plain slab {name}: {plain[name]['value']:.4g} cell-updates/s")
+        for name, maker in (("slab", lambda pr: W.slab_run(args.seed, precision=pr)),
+                            ("gradient", lambda pr: W.gradient_run(args.seed,
+                                                                  precision=pr))):
+            for pname, pr in (("f32", W.F32), ("f64", W.F64)):
+                p = maker(pr)
+                pdt, pst = gpu_pass_rate(P, [p], 1, 1, tune=not args.no_tune)
+                key = f"{name}_{pname}"
+                plain[key] = {"value": p.nz * p.steps / pdt, "ms": pdt * 1e3,
+                              "nz": p.nz, "steps": p.steps,
+                              "cells_per_lane": int(pst["cells_per_lane"]),
+                              "block_steps": int(pst["block_steps"]),
+                              "graph": int(pst["graph"])}
+                log(f"plain {key}: {plain[key]['value']:.4g} cell-updates/s "
+                    f"(C={pst['cells_per_lane']}, T={pst['block_steps']})")
 
     # ---------------------------------------- error and CPU baseline (sample)
     sample = [q.replace(steps=min(q.steps, args.cpu_sample_steps))

@@ -246,6 +246,19 @@ typedef struct gfdtd_stats {
 } gfdtd_stats;
 
 gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
+
+/*
+ * Autotuner: for each (precision, kind) group of the batch, time
+ * trial_blocks launches (0 = 4) of every valid (cells per lane in {4, 8,
+ * 16}, steps per launch in {8, 16, 24, 32, 48, 64}) on the prepared runs
+ * and keep the fastest per cell-update; results of a pass do not depend on
+ * the choice.  Choices are cached in the process by precision, kind, sign
+ * mix and the size scales of the group.  Writes the first group's choice to
+ * *chosen (may be NULL).  Synchronous; leaves the fields to be re-zeroed by
+ * the next gfdtd_batch_run.
+ */
+gfdtd_status gfdtd_batch_autotune(gfdtd_batch *b, int32_t trial_blocks,
+                                  gfdtd_exec *chosen);
 void gfdtd_batch_destroy(gfdtd_batch *b);
 
 /* --------------------------------------------------------------- serving */

@@ -85,6 +85,13 @@ __device__ __forceinline__ int64_t profile_shift(double bS, double tau)
     return (int64_t)rint(bS * tau);
 }
 
+// Same value for |beta S tau| < 2^31 (always the case: |beta S| < 1 and
+// fewer than 2^31 steps), with 32-bit conversions.
+__device__ __forceinline__ int profile_shift32(double bS, double tau)
+{
+    return (int)rint(bS * tau);
+}
+
 __device__ __forceinline__ int64_t clampi(int64_t i, int64_t lo, int64_t hi)
 {
     return i < lo ? lo : (i > hi ? hi : i);
@@ -127,19 +134,20 @@ __device__ __forceinline__ void store_cells(R *__restrict__ p, const R (&v)[C])
     }
 }
 
-// Move a lane-distributed coefficient window by d in {-1, 0, +1} cells
-// (d is the same on every lane).  The value entering at a tile edge is
-// not meaningful; it only ever reaches lanes outside the valid region.
-template <typename R, int C>
-__device__ __forceinline__ void shift_window(R (&a)[C], int64_t d)
+// Move a lane-distributed coefficient window one cell in the direction
+// the profile moves: towards higher cells for v >= 0 (NEG false), lower
+// cells for v < 0.  The value entering at a tile edge is not meaningful;
+// it only ever reaches lanes outside the valid region.
+template <typename R, int C, bool NEG>
+__device__ __forceinline__ void shift_window(R (&a)[C])
 {
-    if (d == 1) {
+    if constexpr (!NEG) {
         const R in = from_left(a[C - 1]);
 #pragma unroll
         for (int c = C - 1; c > 0; --c)
             a[c] = a[c - 1];
         a[0] = in;
-    } else if (d == -1) {
+    } else {
         const R in = from_right(a[0]);
 #pragma unroll
         for (int c = 0; c < C - 1; ++c)
@@ -205,9 +213,11 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     load_cells<R, C>(Bsrc + kb, B);
 
     // coefficients for the first step of the block: E nodes at n0-1/2,
-    // H nodes at n0
-    int64_t mE = profile_shift(bS64, (double)(n0 - 1) + 0.5);
-    int64_t mH = profile_shift(bS64, (double)n0);
+    // H nodes at n0.  Times are exact in FP64 and advanced by 1 per step.
+    double tauH = (double)n0;
+    double tauE = tauH - 0.5;          // = (n0 - 1) + 1/2 exactly
+    int mE = profile_shift32(bS64, tauE);
+    int mH = profile_shift32(bS64, tauH);
     R ce[C], ch[C], ge[C], gh[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -313,11 +323,14 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     for (int s = 0; s < nsub; ++s) {
         const int64_t n = n0 + s;
         if (s > 0) {                      // H coefficients at time n
-            const int64_t m = profile_shift(bS64, (double)n);
-            shift_window<R, C>(ch, m - mH);
-            if constexpr (kMatter)
-                shift_window<R, C>(gh, m - mH);
-            mH = m;
+            tauH += 1.0;
+            const int m = profile_shift32(bS64, tauH);
+            if (m != mH) {
+                shift_window<R, C, NEG>(ch);
+                if constexpr (kMatter)
+                    shift_window<R, C, NEG>(gh);
+                mH = m;
+            }
         }
 
         compute_es();
@@ -379,7 +392,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         }
         // end nodes, at time n+1/2
-        const int64_t mEn = profile_shift(bS64, (double)n + 0.5);
+        tauE += 1.0;
+        const int mEn = profile_shift32(bS64, tauE);
         if (touchL) {
             const int l0 = (int)(-x0 / C);
             if (lane == l0) {
@@ -418,10 +432,12 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             ghosts(B);
 
         // E coefficients at time n+1/2 for the next step
-        shift_window<R, C>(ce, mEn - mE);
-        if constexpr (kMatter)
-            shift_window<R, C>(ge, mEn - mE);
-        mE = mEn;
+        if (mEn != mE) {
+            shift_window<R, C, NEG>(ce);
+            if constexpr (kMatter)
+                shift_window<R, C, NEG>(ge);
+            mE = mEn;
+        }
     }
 
     if (last) {               // the run ends in this block: E at N+1/2

@@ -12,6 +12,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -271,7 +273,7 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 
 // --------------------------------------------------------------- tiling
 
-// Tiling defaults from measurements on MI355X: 8 cells per lane and 32
+// Tiling defaults from measurements on MI355X: 8 cells per lane and 24
 // steps per launch for batches that fill the GPU; 4 cells per lane when the
 // group holds few cells (more, narrower tiles keep more SIMDs busy).
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
@@ -286,7 +288,7 @@ void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
     else if (ex && ex->block_steps > 0)
         T = ex->block_steps;
     else
-        T = 32;
+        T = 24;
     if (max_steps > 0 && T > max_steps)
         T = (int)std::max<int64_t>(1, max_steps);
 }
@@ -397,52 +399,32 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         std::stable_sort(G.members.begin(), G.members.end(), [&](int a, int b) {
             return runs[a].steps > runs[b].steps;
         });
-        std::vector<RunDesc> rd(nr);
-        std::vector<PrepDesc> pd(nr);
-        std::vector<DftDesc> dd(nr);
-        std::vector<TileRef> tiles;
-        G.blocks_of.resize(nr);
-        G.tiles_prefix.assign(nr + 1, 0);
-        const size_t w = G.precision == GFDTD_F32 ? 4 : 8;
+        G.host_pd.assign(nr, PrepDesc{});
+        G.host_dd.assign(nr, DftDesc{});
         G.max_cells = 0;
         G.max_field = 0;
         G.max_pf = 0;
         for (int m = 0; m < nr; ++m) {
             RunHost &r = runs[G.members[m]];
-            int hl, hr;
-            if (!halo_lanes(r.p.beta, G.C, G.T, hl, hr))
-                return fail(GFDTD_E_INVALID,
-                            "block of %d steps too deep for %d cells per lane",
-                            G.T, G.C);
-            const int64_t own = (int64_t)(kWave - hl - hr) * G.C;
-            const int64_t nt = (r.p.nz + own - 1) / own;
-            fill_desc(r, G, hl, hr, own, 0, rd[m], pd[m], dd[m]);
-            for (int64_t t = 0; t < nt; ++t)
-                tiles.push_back(TileRef{m, (int32_t)t});
-            G.tiles_prefix[m + 1] = G.tiles_prefix[m] + nt;
-            G.blocks_of[m] = (r.steps + G.T - 1) / G.T;
+            RunDesc rd;
+            fill_desc(r, G, 1, 1, kWave - 2, 0, rd, G.host_pd[m], G.host_dd[m]);
             G.max_cells = std::max<int64_t>(G.max_cells, std::max(r.p.nz, r.L.nsrc));
             G.max_field = std::max<int64_t>(G.max_field, field_cells(r.p.nz));
             G.max_pf = std::max(G.max_pf, r.p.nprobe * r.p.nfreq);
-            (void)w;
         }
-        G.nblocks = nr ? G.blocks_of[0] : 0;
         Carver tc;
         tc.off = G.table_off;
+        int64_t maxt = 0;
+        for (int i : G.members)
+            maxt += max_tiles_of(runs[i].p.nz);
         G.runs_off = tc.take((size_t)nr * sizeof(RunDesc));
-        G.tiles_off = tc.take(std::max<size_t>(tiles.size(), 1) * sizeof(TileRef));
+        G.tiles_off = tc.take((size_t)std::max<int64_t>(maxt, 1) * sizeof(TileRef));
         G.prep_off = tc.take((size_t)nr * sizeof(PrepDesc));
         G.dft_off = tc.take((size_t)nr * sizeof(DftDesc));
-        G.host_rd = rd;
-        G.host_pd = pd;
-        G.host_dd = dd;
-        G.host_tiles = tiles;
-        if ((e = hipMemcpyAsync(ws + G.runs_off, G.host_rd.data(), nr * sizeof(RunDesc),
-                                hipMemcpyHostToDevice, stream)) ||
-            (e = hipMemcpyAsync(ws + G.tiles_off, G.host_tiles.data(),
-                                G.host_tiles.size() * sizeof(TileRef),
-                                hipMemcpyHostToDevice, stream)) ||
-            (e = hipMemcpyAsync(ws + G.prep_off, G.host_pd.data(), nr * sizeof(PrepDesc),
+        gfdtd_status st = build_tiles(G);
+        if (st != GFDTD_OK)
+            return st;
+        if ((e = hipMemcpyAsync(ws + G.prep_off, G.host_pd.data(), nr * sizeof(PrepDesc),
                                 hipMemcpyHostToDevice, stream)) ||
             (e = hipMemcpyAsync(ws + G.dft_off, G.host_dd.data(), nr * sizeof(DftDesc),
                                 hipMemcpyHostToDevice, stream)))
@@ -458,14 +440,205 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
     if ((e = hipEventCreate(&ev[0])) || (e = hipEventCreate(&ev[1])) ||
         (e = hipEventCreate(&ev[2])) || (e = hipEventCreate(&ev[3])))
         return hip_fail(e, "create events");
-    // launch statistics of one pass
+    count_launches();
+    if (use_graph == 1 || (use_graph < 0 && auto_graph()))
+        return build_graphs();
+    return GFDTD_OK;
+}
+
+void Batch::count_launches()
+{
+    launches = 0;
+    tiles_total = 0;
     for (auto &G : groups)
         for (int64_t b = 0; b < G.nblocks; ++b) {
             launches += 1;
             tiles_total += live_tiles(G, b);
         }
-    if (use_graph == 1 || (use_graph < 0 && auto_graph()))
-        return build_graphs();
+}
+
+// Run and tile tables of a group for its current (C, T); uploads them on
+// the batch stream.
+gfdtd_status Batch::build_tiles(Group &G)
+{
+    const int nr = (int)G.members.size();
+    G.host_rd.assign(nr, RunDesc{});
+    G.host_tiles.clear();
+    G.blocks_of.assign(nr, 0);
+    G.tiles_prefix.assign(nr + 1, 0);
+    for (int m = 0; m < nr; ++m) {
+        RunHost &r = runs[G.members[m]];
+        r.T = G.T;
+        int hl, hr;
+        if (!halo_lanes(r.p.beta, G.C, G.T, hl, hr))
+            return fail(GFDTD_E_INVALID, "block of %d steps too deep for %d cells per lane",
+                        G.T, G.C);
+        const int64_t own = (int64_t)(kWave - hl - hr) * G.C;
+        const int64_t nt = (r.p.nz + own - 1) / own;
+        PrepDesc pd;
+        DftDesc dd;
+        fill_desc(r, G, hl, hr, own, 0, G.host_rd[m], pd, dd);
+        for (int64_t t = 0; t < nt; ++t)
+            G.host_tiles.push_back(TileRef{m, (int32_t)t});
+        G.tiles_prefix[m + 1] = G.tiles_prefix[m] + nt;
+        G.blocks_of[m] = (r.steps + G.T - 1) / G.T;
+    }
+    G.nblocks = nr ? G.blocks_of[0] : 0;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ws + G.runs_off, G.host_rd.data(), nr * sizeof(RunDesc),
+                            hipMemcpyHostToDevice, stream)) ||
+        (!G.host_tiles.empty() &&
+         (e = hipMemcpyAsync(ws + G.tiles_off, G.host_tiles.data(),
+                             G.host_tiles.size() * sizeof(TileRef), hipMemcpyHostToDevice,
+                             stream))))
+        return hip_fail(e, "upload run tables");
+    return GFDTD_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+
+namespace {
+struct TuneKey {
+    int precision, kind, neg, runs_log2, cells_log2, steps_log2;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(precision, kind, neg, runs_log2, cells_log2, steps_log2) <
+               std::tie(o.precision, o.kind, o.neg, o.runs_log2, o.cells_log2, o.steps_log2);
+    }
+};
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+std::mutex g_tune_mutex;
+
+int ilog2(double x) { return x < 1.0 ? 0 : (int)std::floor(std::log2(x)); }
+}  // namespace
+
+// Time `trial` blocks of each candidate (cells per lane C, steps per launch
+// T) on the prepared runs and keep the fastest per cell-update; the result
+// of a pass does not depend on the choice.  Choices are cached in memory by
+// the group's precision, kind, sign mix and the size scales of its runs.
+gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
+{
+    hipError_t e;
+    gfdtd_status st;
+    if (trial < 1)
+        trial = 4;
+    hipEvent_t t0, t1;
+    if ((e = hipEventCreate(&t0)) || (e = hipEventCreate(&t1)))
+        return hip_fail(e, "create events");
+    for (auto &G : groups) {
+        double cells = 0.0, steps = 0.0;
+        int neg = 0;
+        for (int i : G.members) {
+            cells += (double)runs[i].p.nz;
+            steps = std::max(steps, (double)runs[i].steps);
+            neg |= runs[i].p.beta < 0.0 ? 2 : 1;
+        }
+        const TuneKey key{G.precision, G.kind, neg, ilog2((double)G.members.size()),
+                          ilog2(cells), ilog2(steps)};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mutex);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                G.C = it->second.first;
+                G.T = it->second.second;
+                if ((st = build_tiles(G)) != GFDTD_OK)
+                    return st;
+                continue;
+            }
+        }
+        const int defC = G.C, defT = G.T;
+        int bestC = G.C, bestT = G.T;
+        double best = 1e300, def_time = 1e300;
+        const int Cs[] = {4, 8, 16};
+        const int Ts[] = {8, 16, 24, 32, 48, 64};
+        for (int C : Cs)
+            for (int T : Ts) {
+                if ((double)T > steps && T != 8)
+                    continue;
+                bool ok = true;
+                int hl, hr;
+                for (int i : G.members)
+                    ok = ok && halo_lanes(runs[i].p.beta, C, T, hl, hr);
+                if (!ok)
+                    continue;
+                G.C = C;
+                G.T = T;
+                if ((st = build_tiles(G)) != GFDTD_OK)
+                    return st;
+                const int64_t nb = std::min<int64_t>(trial + 1, G.nblocks);
+                if (nb < 1)
+                    continue;
+                double upd = 0.0;
+                for (int64_t b = 1; b < nb; ++b)
+                    for (size_t m = 0; m < G.members.size() && G.blocks_of[m] > b; ++m) {
+                        const RunHost &r = runs[G.members[m]];
+                        upd += (double)r.p.nz *
+                               (double)std::min<int64_t>(T, r.steps - b * (int64_t)T);
+                    }
+                auto launch = [&](int64_t b) {
+                    return launch_tiles(G.precision, G.kind, C,
+                                        reinterpret_cast<const RunDesc *>(ws + G.runs_off),
+                                        reinterpret_cast<const TileRef *>(ws + G.tiles_off),
+                                        b, T, live_tiles(G, b), stream);
+                };
+                if ((e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + G.prep_off),
+                                     (int)G.members.size(), G.max_field, G.precision,
+                                     stream)) ||
+                    (e = launch(0)) || (e = hipEventRecord(t0, stream)))
+                    return hip_fail(e, "autotune trial");
+                for (int64_t b = 1; b < nb; ++b)
+                    if ((e = launch(b)))
+                        return hip_fail(e, "autotune trial");
+                float ms = 0.f;
+                if ((e = hipEventRecord(t1, stream)) || (e = hipEventSynchronize(t1)) ||
+                    (e = hipEventElapsedTime(&ms, t0, t1)))
+                    return hip_fail(e, "autotune timing");
+                const double per = upd > 0.0 ? ms / upd : (double)ms;
+                if (C == defC && T == defT)
+                    def_time = per;
+                if (per < best) {
+                    best = per;
+                    bestC = C;
+                    bestT = T;
+                }
+            }
+        // keep the default unless a candidate is clearly faster (trial
+        // timings carry a few per cent of noise)
+        if (def_time < 1e300 && best > def_time / 1.03) {
+            bestC = defC;
+            bestT = defT;
+        }
+        G.C = bestC;
+        G.T = bestT;
+        if ((st = build_tiles(G)) != GFDTD_OK)
+            return st;
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        g_tune_cache[key] = {bestC, bestT};
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if ((e = hipStreamSynchronize(stream)))
+        return hip_fail(e, "autotune");
+    count_launches();
+    if (graph_on) {
+        for (int k = 0; k < 3; ++k) {
+            if (execs[k])
+                (void)hipGraphExecDestroy(execs[k]);
+            if (graphs[k])
+                (void)hipGraphDestroy(graphs[k]);
+            execs[k] = nullptr;
+            graphs[k] = nullptr;
+        }
+        graph_on = false;
+        if ((st = build_graphs()) != GFDTD_OK)
+            return st;
+    }
+    if (chosen && chosen->struct_size >= sizeof(gfdtd_exec) && !groups.empty()) {
+        chosen->variant = GFDTD_VARIANT_TILED;
+        chosen->cells_per_lane = groups[0].C;
+        chosen->block_steps = groups[0].T;
+        chosen->use_graph = graph_on ? 1 : 0;
+    }
     return GFDTD_OK;
 }
 
@@ -612,7 +785,7 @@ gfdtd_status Batch::enqueue_dft(hipStream_t s)
 gfdtd_status Batch::build_graphs()
 {
     hipError_t e;
-    if ((e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)))
+    if (!cap_stream && (e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking)))
         return hip_fail(e, "create capture stream");
     for (int k = 0; k < 3; ++k) {
         if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed)))
@@ -910,6 +1083,15 @@ gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s)
         return fail(GFDTD_E_INVALID, "bad arguments");
     reinterpret_cast<const Batch *>(b)->stats(s);
     return GFDTD_OK;
+}
+
+gfdtd_status gfdtd_batch_autotune(gfdtd_batch *b, int32_t trial_blocks,
+                                  gfdtd_exec *chosen)
+{
+    clear_error();
+    if (!b)
+        return fail(GFDTD_E_INVALID, "batch is NULL");
+    return reinterpret_cast<Batch *>(b)->autotune(trial_blocks, chosen);
 }
 
 void gfdtd_batch_destroy(gfdtd_batch *b) { delete reinterpret_cast<Batch *>(b); }

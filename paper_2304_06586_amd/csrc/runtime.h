@@ -103,6 +103,9 @@ struct Batch {
     gfdtd_status enqueue_steps(hipStream_t s);
     gfdtd_status enqueue_dft(hipStream_t s);
     gfdtd_status build_graphs();
+    gfdtd_status build_tiles(Group &G);
+    void count_launches();
+    gfdtd_status autotune(int trial, gfdtd_exec *chosen);
     gfdtd_status run();
     gfdtd_status collect(gfdtd_result *outs);
     void stats(gfdtd_stats *s) const;

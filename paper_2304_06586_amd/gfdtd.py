@@ -129,6 +129,7 @@ EXPORTS = {
     "gfdtd_batch_run": (C.c_int, [C.c_void_p]),
     "gfdtd_batch_collect": (C.c_int, [C.c_void_p, C.POINTER(gfdtd_result)]),
     "gfdtd_batch_stats": (C.c_int, [C.c_void_p, C.POINTER(gfdtd_stats)]),
+    "gfdtd_batch_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(gfdtd_exec)]),
     "gfdtd_batch_destroy": (None, [C.c_void_p]),
     "gfdtd_server_create": (C.c_int, [C.POINTER(gfdtd_server_config),
                                       C.POINTER(C.c_void_p)]),
@@ -378,6 +379,14 @@ class Batch:
         for o, r in zip(outs, res):
             o.struct = r
         return [o.as_dict() for o in outs]
+
+    def autotune(self, trial_blocks: int = 4) -> Dict[str, int]:
+        """Pick cells per lane and steps per launch by timing trial launches
+        on this batch (results do not depend on the choice)."""
+        e = _exec_struct()
+        _check(self._lib.gfdtd_batch_autotune(self._h, int(trial_blocks), C.byref(e)))
+        return {"cells_per_lane": e.cells_per_lane, "block_steps": e.block_steps,
+                "graph": e.use_graph}
 
     def stats(self) -> Dict[str, float]:
         s = gfdtd_stats()

@@ -196,3 +196,55 @@ def test_crystal_batch_sample(P):
     got = P.gfdtd_solve_batch(probs)
     for p, g in zip(probs, got):
         compare(g, oracle.solve(p), TOL64, p.label)
+
+
+def test_autotune_keeps_results_bitwise(P):
+    """The autotuner changes only the tiling: same bits before and after,
+    with and without graph replay."""
+    probs = [W.small_case(n, s, b, structure="crystal", seed=i, nprobe=3)
+             for i, (n, s, b) in enumerate([(3000, 700, 0.3), (1500, 900, -0.25),
+                                            (5000, 300, 0.1)])]
+    for graph in (0, 1):
+        with P.Batch(probs, use_graph=graph) as b:
+            b.run()
+            ref = b.collect()
+            chosen = b.autotune(trial_blocks=3)
+            assert chosen["cells_per_lane"] in (4, 8, 16)
+            assert chosen["block_steps"] in (8, 16, 24, 32, 48, 64)
+            b.run()
+            got = b.collect()
+        for x, y in zip(got, ref):
+            for k in ("trace", "dft", "d", "b"):
+                assert np.array_equal(x[k], y[k]), k
+
+
+def test_blowup_is_reported_per_run(P):
+    """A run forced past the pre-flight (|beta| n > 1 with
+    GFDTD_FLAG_ALLOW_UNSTABLE) overflows; the watchdog marks that run
+    GFDTD_E_BLOWUP and its batch neighbour is unaffected."""
+    bad = W.small_case(400, 2000, 0.3, seed=1, structure="uniform",
+                       precision=W.F32)
+    # vacuum, beta = 0.9 at S = 0.9: beyond S <= n/(1 + n beta); the
+    # amplification factor is 4.4 per step
+    bad = bad.replace(eps_rest=np.ones(400), mu_rest=np.ones(400), beta=0.9,
+                      courant=0.9, flags=W.FLAG_ALLOW_UNSTABLE)
+    good = W.small_case(400, 600, 0.3, seed=2, precision=W.F32)
+    out = P.gfdtd_solve_batch([bad, good])
+    assert out[0]["status"] == P.gfdtd.GFDTD_E_BLOWUP
+    assert out[1]["status"] == 0
+    alone = P.gfdtd_solve(good)
+    assert np.array_equal(out[1]["trace"], alone["trace"])
+
+
+def test_gradient_full_size_fp32_against_fp64(P):
+    """Moving-matter gradient at full size (2^20 cells, 2^18 steps): the
+    FP32 path (FP64 shifts, coefficients and DFT) against the FP64 path on
+    the probe spectra and traces."""
+    p64 = W.gradient_run(0, precision=W.F64)
+    a = P.gfdtd_solve(p64, fields=False)
+    b = P.gfdtd_solve(p64.replace(precision=W.F32), fields=False)
+    e_dft = rel(b["dft"], a["dft"])
+    e_tr = rel(b["trace"], a["trace"])
+    print(f"gradient 2^20 x 2^18: FP32 vs FP64 dft {e_dft:.2e} trace {e_tr:.2e}")
+    assert a["status"] == 0 and b["status"] == 0
+    assert e_dft < 1e-3 and e_tr < 1e-3
