@@ -147,7 +147,7 @@ def main():
     ap.add_argument("--block-steps", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample-runs", type=int, default=64)
+    ap.add_argument("--cpu-sample-runs", type=int, default=384)
     ap.add_argument("--cpu-sample-steps", type=int, default=6000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
