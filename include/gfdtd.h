@@ -17,7 +17,9 @@
  * (Courant number, below eq. (10)), beta = v/c.
  *
  * Grid: nz E nodes k = 0..nz-1 (D_x, E*_x at times n+1/2) and nz-1 H nodes
- * j = 0..nz-2 at positions j+1/2 (B_y, H*_y at integer times n).
+ * j = 0..nz-2 at positions j+1/2 (B_y, H*_y at integer times n).  With
+ * periodic ends (a ring) there are nz H nodes and node nz-1 neighbours
+ * node 0.
  *
  * Conventions
  *  - Every function returns a gfdtd_status; nothing throws across the ABI.
@@ -79,6 +81,12 @@ const char *gfdtd_last_error(void);
 
 #define GFDTD_ABC_MUR1 0     /* first-order Mur on D at both end nodes      */
 #define GFDTD_ABC_PEC 1      /* D = 0 at both end nodes                     */
+#define GFDTD_ABC_PERIODIC 2 /* a ring: nz E and nz H nodes, node nz-1 next
+                                to node 0; every index (fields, rest cells,
+                                moving-profile samples) wraps modulo nz.
+                                The uniform-medium case is the plane-wave
+                                setting of the stability analysis (Section
+                                5, App. A, Fig. 4)                         */
 
 #define GFDTD_FLAG_RECORD_TRACE 1u   /* copy probe time traces on collect  */
 #define GFDTD_FLAG_ALLOW_UNSTABLE 2u /* skip the pre-flight rejection      */
@@ -93,12 +101,16 @@ const char *gfdtd_last_error(void);
  *               (covering z in [i-1/2, i+1/2) at t = 0), i = 0..nz-1;
  *  mu_rest[i]   rest permeability mu' of the cell centred on H node i
  *               (covering [i, i+1)); entry nz-1 is read only by the
- *               moving-matter end treatment and may be any positive value.
+ *               moving-matter end treatment and by rings, and may
+ *               otherwise be any positive value.
  *  The profile moves rigidly at beta (eq. (5): eps(z - v t)), in whole
  *  cells: at time tau*S it has moved by m = rint(beta*S*tau) cells and a
- *  node at lattice index x reads rest cell clamp(x - m).  E nodes read
- *  at tau = n+1/2, H nodes at tau = n.  For moving matter both eps' and
- *  mu' are read at the node's own lattice index.
+ *  node at lattice index x reads rest cell clamp(x - m) (on a ring
+ *  (x - m) mod nz).  E nodes read at tau = n+1/2, H nodes at tau = n.
+ *  For moving matter both eps' and mu' are read at the node's own
+ *  lattice index.
+ *  Initial state: all fields zero, or D^{1/2} = init_d and B^0 = init_b
+ *  when given (E*^{1/2} then follows from them by (10c)).
  *  Source: soft source added to D at src_cell after (10b) of step n,
  *    src_amp * sin(src_omega (t - src_t0) + src_phase)
  *            * exp(-((t - src_t0)/src_tau)^2),  t = n S,
@@ -122,10 +134,13 @@ typedef struct gfdtd_problem {
     double beta;                 /* v/c, |beta| < 1                        */
     const double *eps_rest;      /* host, nz, > 0 and finite               */
     const double *mu_rest;       /* host, nz, > 0 and finite               */
-    int64_t src_cell;            /* 1..nz-2                                */
+    int64_t src_cell;            /* 1..nz-2 (ring: 0..nz-1)                */
     double src_amp, src_omega, src_t0, src_tau, src_phase, src_t_off;
     const int64_t *probe_cells;  /* host, nprobe, each in 0..nz-1          */
     const double *omegas;        /* host, nfreq                            */
+    const double *init_d;        /* host, nz finite values, or NULL        */
+    const double *init_b;        /* host, nz finite values (entry nz-1 is
+                                    read on a ring only), or NULL          */
 } gfdtd_problem;
 
 /*
@@ -135,7 +150,8 @@ typedef struct gfdtd_problem {
  *           GFDTD_FLAG_RECORD_TRACE);
  *  dft_re/im nprobe*nfreq doubles, probe q at row q;
  *  final_d  nz doubles: D^{steps+1/2} (converted from the run precision);
- *  final_b  nz doubles: B^{steps} at H nodes 0..nz-2, last entry 0.
+ *  final_b  nz doubles: B^{steps} at H nodes 0..nz-2, last entry 0
+ *           (on a ring all nz H nodes).
  */
 typedef struct gfdtd_result {
     uint32_t struct_size;

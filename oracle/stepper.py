@@ -71,9 +71,15 @@ def solve(problem, steps: Optional[int] = None,
 
     Returns a dict with 'trace' (nprobe, steps), 'dft' (nprobe, nfreq,
     complex), and, if `fields`, 'd', 'b', 'es', 'hs' (nz each) at the end.
+    The initial fields default to the problem's init_d / init_b (zero when
+    absent).
     """
     lib = _load()
     p = problem
+    if init_d is None:
+        init_d = getattr(p, "init_d", None)
+    if init_b is None:
+        init_b = getattr(p, "init_b", None)
     steps = int(p.steps if steps is None else steps)
     nz = int(p.nz)
     eps = np.ascontiguousarray(p.eps_rest, dtype=np.float64)

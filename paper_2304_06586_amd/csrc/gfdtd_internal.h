@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "gfdtd.h"
+
 namespace gfdtd {
 
 constexpr int kWave = 64;            // CDNA wavefront width
@@ -31,7 +33,7 @@ struct RunDesc {
     int32_t hl;            // halo lanes left of the owned lanes
     int32_t hr;            // halo lanes right of the owned lanes
     int32_t nprobe;
-    int32_t abc;           // GFDTD_ABC_*
+    int32_t abc;           // GFDTD_ABC_* (GFDTD_ABC_PERIODIC: a ring)
     int32_t pad0;
     void *D[2];            // ping-pong D (run precision)
     void *B[2];            // ping-pong B
@@ -58,6 +60,8 @@ struct PrepDesc {
     double amp, omega, t0, tau, phase;
     int32_t kind;
     int32_t precision;
+    int32_t abc;
+    int32_t pad0;
     const double *eps;     // rest profile (device copy)
     const double *mu;
     void *cE;
@@ -68,6 +72,8 @@ struct PrepDesc {
     double *src;
     void *fields[4];       // D0, D1, B0, B1 (offset by kPad)
     int64_t field_cells;   // nz + 2 kPad
+    const double *init_d;  // initial D^{1/2} (device copy, nz) or null
+    const double *init_b;  // initial B^0 (device copy, nz) or null
 };
 
 struct DftDesc {
@@ -86,9 +92,22 @@ hipError_t launch_prep(const PrepDesc *dev_descs, int count, int max_cells,
 hipError_t launch_zero(const PrepDesc *dev_descs, int count,
                        int64_t max_field_cells, int precision,
                        hipStream_t stream);
-hipError_t launch_tiles(int precision, int kind, int C, const RunDesc *runs,
-                        const TileRef *tiles, int64_t block, int T,
-                        int ntiles, hipStream_t stream);
+hipError_t launch_init(const PrepDesc *dev_descs, int count, int64_t max_nz,
+                       int precision, hipStream_t stream);
+hipError_t launch_tiles(int precision, int kind, bool ring, int C,
+                        const RunDesc *runs, const TileRef *tiles, int64_t block,
+                        int T, int ntiles, hipStream_t stream);
+
+// Runs are stepped in groups that share one kernel instantiation: by
+// precision, kind and ring (periodic ends) or not.
+constexpr int kGroups = 8;
+inline int group_of(int precision, int kind, int abc)
+{
+    return precision * 4 + kind * 2 + (abc == GFDTD_ABC_PERIODIC ? 1 : 0);
+}
+inline int group_precision(int g) { return g >> 2; }
+inline int group_kind(int g) { return (g >> 1) & 1; }
+inline bool group_ring(int g) { return (g & 1) != 0; }
 hipError_t launch_dft(const DftDesc *dev_descs, int count, int max_pf,
                       hipStream_t stream);
 

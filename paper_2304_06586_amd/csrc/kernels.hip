@@ -97,6 +97,19 @@ __device__ __forceinline__ int64_t clampi(int64_t i, int64_t lo, int64_t hi)
     return i < lo ? lo : (i > hi ? hi : i);
 }
 
+// i mod n in [0, n), for any sign of i (ring indexing).
+__device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n)
+{
+    const int64_t r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Next index on a ring of n >= 2 cells.
+__device__ __forceinline__ int64_t ring_next(int64_t i, int64_t n)
+{
+    return i + 1 == n ? 0 : i + 1;
+}
+
 template <typename R, int C>
 __device__ __forceinline__ void load_cells(const R *__restrict__ p, R (&v)[C])
 {
@@ -170,7 +183,7 @@ __device__ __forceinline__ R pick(const R (&a)[C], int idx)
 
 // ------------------------------------------------------------- the tile
 
-template <typename R, int C, int KIND, bool NEG>
+template <typename R, int C, int KIND, bool NEG, bool RING>
 __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                                           int tile, int64_t block, int T)
 {
@@ -208,9 +221,22 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     const R *__restrict__ cHp = static_cast<const R *>(rd->cH);
     const R *__restrict__ gBp = static_cast<const R *>(rd->gB);
 
+    // On a ring every index is taken modulo nz: a window that crosses an
+    // end (or a ring shorter than the window) loads cell by cell.
+    const int64_t kw = RING ? wrapi(kb, nz) : kb;
     R D[C], B[C];
-    load_cells<R, C>(Dsrc + kb, D);
-    load_cells<R, C>(Bsrc + kb, B);
+    if (RING && (x0 < 0 || x0 + W > nz)) {
+        int64_t i = kw;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            D[c] = Dsrc[i];
+            B[c] = Bsrc[i];
+            i = ring_next(i, nz);
+        }
+    } else {
+        load_cells<R, C>(Dsrc + kb, D);
+        load_cells<R, C>(Bsrc + kb, B);
+    }
 
     // coefficients for the first step of the block: E nodes at n0-1/2,
     // H nodes at n0.  Times are exact in FP64 and advanced by 1 per step.
@@ -219,20 +245,37 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     int mE = profile_shift32(bS64, tauE);
     int mH = profile_shift32(bS64, tauH);
     R ce[C], ch[C], ge[C], gh[C];
+    if constexpr (RING) {
+        int64_t iE = wrapi(kb - mE, nz);
+        int64_t iH = wrapi(kb - mH, nz);
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int64_t iE = clampi(kb + c - mE, 0, nz - 1);
-        const int64_t iH = clampi(kb + c - mH, 0, nz - 2);
-        ce[c] = cEp[iE];
-        ch[c] = cHp[iH];
-        if constexpr (kMatter) {
-            ge[c] = gBp[iE];
-            gh[c] = gBp[iH];
+        for (int c = 0; c < C; ++c) {
+            ce[c] = cEp[iE];
+            ch[c] = cHp[iH];
+            if constexpr (kMatter) {
+                ge[c] = gBp[iE];
+                gh[c] = gBp[iH];
+            }
+            iE = ring_next(iE, nz);
+            iH = ring_next(iH, nz);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int64_t iE = clampi(kb + c - mE, 0, nz - 1);
+            const int64_t iH = clampi(kb + c - mH, 0, nz - 2);
+            ce[c] = cEp[iE];
+            ch[c] = cHp[iH];
+            if constexpr (kMatter) {
+                ge[c] = gBp[iE];
+                gh[c] = gBp[iH];
+            }
         }
     }
 
-    const bool touchL = x0 < 0;              // holds E node 0 (and ghosts)
-    const bool touchR = x0 + W > nz - 1;     // holds node nz-1 (and ghosts)
+    // a ring has no ends
+    const bool touchL = !RING && x0 < 0;            // E node 0 (and ghosts)
+    const bool touchR = !RING && x0 + W > nz - 1;   // node nz-1 (and ghosts)
 
     // Off the grid B takes the edge value (zero-gradient extension).
     auto ghosts = [&](R (&Bv)[C]) __attribute__((always_inline)) {
@@ -256,10 +299,29 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     if (touchL || touchR)
         ghosts(B);
 
+    // The source cell: lane ls, register cs.  On a ring every copy of the
+    // source cell inside the window takes the source: bit c of smask for
+    // register c of this lane.
     const int64_t ks = rd->src_cell;
-    const bool hasSrc = rd->nsrc > 0 && ks >= x0 && ks < x0 + W;
-    const int ls = hasSrc ? (int)((ks - x0) / C) : -1;
-    const int cs = hasSrc ? (int)((ks - x0) % C) : 0;
+    bool hasSrc = false;
+    int ls = -1, cs = 0;
+    unsigned smask = 0u;
+    if (rd->nsrc > 0) {
+        if constexpr (RING) {
+            int64_t i = kw;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (i == ks)
+                    smask |= 1u << c;
+                i = ring_next(i, nz);
+            }
+            hasSrc = __ballot(smask != 0u) != 0;
+        } else if (ks >= x0 && ks < x0 + W) {
+            hasSrc = true;
+            ls = (int)((ks - x0) / C);
+            cs = (int)((ks - x0) % C);
+        }
+    }
     const int64_t own_lo = x0 + (int64_t)hl * C;
     const int64_t own_hi = x0 + W - (int64_t)hr * C;
 
@@ -384,7 +446,14 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // soft source
         if (hasSrc && n <= rd->nsrc) {
             const R g = (R)rd->src[n - 1];
-            if (lane == ls) {
+            if constexpr (RING) {
+                if (smask) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c)
+                        if ((smask >> c) & 1u)
+                            Dn[c] += g;
+                }
+            } else if (lane == ls) {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
                     if (c == cs)
@@ -451,7 +520,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     }
 }
 
-template <typename R, int C, int KIND>
+template <typename R, int C, int KIND, bool RING>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
     const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
     int64_t block, int T, int ntiles)
@@ -463,12 +532,12 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
     const TileRef ref = tiles[t];
     const RunDesc *rd = runs + ref.run;
     if (rd->neg)
-        tile_body<R, C, KIND, true>(rd, ref.tile, block, T);
+        tile_body<R, C, KIND, true, RING>(rd, ref.tile, block, T);
     else
-        tile_body<R, C, KIND, false>(rd, ref.tile, block, T);
+        tile_body<R, C, KIND, false, RING>(rd, ref.tile, block, T);
 }
 
-template <typename R, int KIND>
+template <typename R, int KIND, bool RING>
 static hipError_t launch_tiles_c(int C, const RunDesc *runs,
                                  const TileRef *tiles, int64_t block, int T,
                                  int ntiles, hipStream_t stream)
@@ -479,15 +548,15 @@ static hipError_t launch_tiles_c(int C, const RunDesc *runs,
     const dim3 blk(kWave * kWavesPerGroup);
     switch (C) {
     case 4:
-        hipLaunchKernelGGL((k_tiles<R, 4, KIND>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 4, KIND, RING>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     case 8:
-        hipLaunchKernelGGL((k_tiles<R, 8, KIND>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 8, KIND, RING>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     case 16:
-        hipLaunchKernelGGL((k_tiles<R, 16, KIND>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 16, KIND, RING>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     default:
@@ -496,18 +565,25 @@ static hipError_t launch_tiles_c(int C, const RunDesc *runs,
     return hipGetLastError();
 }
 
-hipError_t launch_tiles(int precision, int kind, int C, const RunDesc *runs,
-                        const TileRef *tiles, int64_t block, int T,
-                        int ntiles, hipStream_t stream)
+template <typename R>
+static hipError_t launch_tiles_r(int kind, bool ring, int C, const RunDesc *runs,
+                                 const TileRef *tiles, int64_t block, int T,
+                                 int ntiles, hipStream_t stream)
 {
-    if (precision == GFDTD_F32) {
-        return kind == GFDTD_MATTER
-                   ? launch_tiles_c<float, GFDTD_MATTER>(C, runs, tiles, block, T, ntiles, stream)
-                   : launch_tiles_c<float, GFDTD_MODULATION>(C, runs, tiles, block, T, ntiles, stream);
-    }
-    return kind == GFDTD_MATTER
-               ? launch_tiles_c<double, GFDTD_MATTER>(C, runs, tiles, block, T, ntiles, stream)
-               : launch_tiles_c<double, GFDTD_MODULATION>(C, runs, tiles, block, T, ntiles, stream);
+    if (kind == GFDTD_MATTER)
+        return ring ? launch_tiles_c<R, GFDTD_MATTER, true>(C, runs, tiles, block, T, ntiles, stream)
+                    : launch_tiles_c<R, GFDTD_MATTER, false>(C, runs, tiles, block, T, ntiles, stream);
+    return ring ? launch_tiles_c<R, GFDTD_MODULATION, true>(C, runs, tiles, block, T, ntiles, stream)
+                : launch_tiles_c<R, GFDTD_MODULATION, false>(C, runs, tiles, block, T, ntiles, stream);
+}
+
+hipError_t launch_tiles(int precision, int kind, bool ring, int C,
+                        const RunDesc *runs, const TileRef *tiles, int64_t block,
+                        int T, int ntiles, hipStream_t stream)
+{
+    if (precision == GFDTD_F32)
+        return launch_tiles_r<float>(kind, ring, C, runs, tiles, block, T, ntiles, stream);
+    return launch_tiles_r<double>(kind, ring, C, runs, tiles, block, T, ntiles, stream);
 }
 
 // ------------------------------------------------------------- set-up
@@ -599,6 +675,45 @@ __global__ __launch_bounds__(256) void k_zero(const PrepDesc *__restrict__ descs
              i < words16; i += (int64_t)gridDim.x * blockDim.x)
             p[i] = make_uint4(0u, 0u, 0u, 0u);
     }
+}
+
+// Initial state D^{1/2}, B^0 from FP64 copies, rounded to the run
+// precision, into the first half of each field pair (after k_zero).  Off a
+// ring, B has nz-1 nodes and its last slot stays zero.
+template <typename R>
+__device__ __forceinline__ void init_cell(const PrepDesc &d, int64_t i)
+{
+    if (d.init_d)
+        static_cast<R *>(d.fields[0])[i] = (R)d.init_d[i];
+    if (d.init_b && (d.abc == GFDTD_ABC_PERIODIC || i < d.nz - 1))
+        static_cast<R *>(d.fields[2])[i] = (R)d.init_b[i];
+}
+
+__global__ __launch_bounds__(256) void k_init(const PrepDesc *__restrict__ descs)
+{
+    const PrepDesc &d = descs[blockIdx.y];
+    if (!d.init_d && !d.init_b)
+        return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d.nz;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (d.precision == GFDTD_F32)
+            init_cell<float>(d, i);
+        else
+            init_cell<double>(d, i);
+    }
+}
+
+hipError_t launch_init(const PrepDesc *dev_descs, int count, int64_t max_nz,
+                       int precision, hipStream_t stream)
+{
+    (void)precision;
+    if (count <= 0)
+        return hipSuccess;
+    int64_t bx = (max_nz + 255) / 256;
+    bx = bx < 1 ? 1 : (bx > 512 ? 512 : bx);
+    hipLaunchKernelGGL(k_init, dim3((unsigned)bx, count), dim3(256), 0, stream,
+                       dev_descs);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(const PrepDesc *dev_descs, int count,

@@ -61,9 +61,9 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
         return fail(GFDTD_E_INVALID, "unknown kind %d", p->kind);
     if (p->precision != GFDTD_F32 && p->precision != GFDTD_F64)
         return fail(GFDTD_E_INVALID, "unknown precision %d", p->precision);
-    if (p->abc != GFDTD_ABC_MUR1 && p->abc != GFDTD_ABC_PEC)
-        return fail(p->abc == 2 ? GFDTD_E_UNSUPPORTED : GFDTD_E_INVALID,
-                    "end condition %d not available", p->abc);
+    if (p->abc != GFDTD_ABC_MUR1 && p->abc != GFDTD_ABC_PEC &&
+        p->abc != GFDTD_ABC_PERIODIC)
+        return fail(GFDTD_E_INVALID, "unknown end condition %d", p->abc);
     if (p->nz < 8)
         return fail(GFDTD_E_INVALID, "nz = %lld < 8", (long long)p->nz);
     if (p->nz > (int64_t(1) << 31))
@@ -82,9 +82,11 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
         if (!finite_pos(p->eps_rest[i]) || !finite_pos(p->mu_rest[i]))
             return fail(GFDTD_E_INVALID, "eps_rest/mu_rest[%lld] not finite > 0",
                         (long long)i);
-    if (p->src_cell < 1 || p->src_cell > p->nz - 2)
-        return fail(GFDTD_E_INVALID, "src_cell %lld outside 1..nz-2",
-                    (long long)p->src_cell);
+    const bool ring = p->abc == GFDTD_ABC_PERIODIC;
+    if (ring ? (p->src_cell < 0 || p->src_cell > p->nz - 1)
+             : (p->src_cell < 1 || p->src_cell > p->nz - 2))
+        return fail(GFDTD_E_INVALID, "src_cell %lld outside %s",
+                    (long long)p->src_cell, ring ? "0..nz-1" : "1..nz-2");
     if (!std::isfinite(p->src_amp) || !std::isfinite(p->src_omega) ||
         !std::isfinite(p->src_t0) || !std::isfinite(p->src_phase) ||
         !std::isfinite(p->src_t_off))
@@ -105,6 +107,11 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
     for (int f = 0; f < p->nfreq; ++f)
         if (!std::isfinite(p->omegas[f]))
             return fail(GFDTD_E_INVALID, "omegas[%d] not finite", f);
+    for (int64_t i = 0; i < p->nz; ++i)
+        if ((p->init_d && !std::isfinite(p->init_d[i])) ||
+            (p->init_b && !std::isfinite(p->init_b[i])))
+            return fail(GFDTD_E_INVALID, "init_d/init_b[%lld] not finite",
+                        (long long)i);
     return GFDTD_OK;
 }
 
@@ -255,6 +262,58 @@ void carve_run(Carver &cv, const gfdtd_problem *p, int64_t steps, RunLayout &L)
     const size_t fb = (size_t)field_cells(p->nz) * w;
     for (int f = 0; f < 4; ++f)
         L.field[f] = cv.take(fb);
+    L.has_init_d = p->init_d != nullptr;
+    L.has_init_b = p->init_b != nullptr;
+    L.init_d = L.has_init_d ? cv.take(nz * 8) : 0;
+    L.init_b = L.has_init_b ? cv.take(nz * 8) : 0;
+}
+
+RunHost make_run_host(const gfdtd_problem &p, int64_t steps)
+{
+    RunHost r;
+    r.p = p;
+    r.steps = steps;
+    r.eps.assign(p.eps_rest, p.eps_rest + p.nz);
+    r.mu.assign(p.mu_rest, p.mu_rest + p.nz);
+    r.probes.assign(p.probe_cells, p.probe_cells + p.nprobe);
+    r.omegas.assign(p.omegas, p.omegas + p.nfreq);
+    if (p.init_d)
+        r.init_d.assign(p.init_d, p.init_d + p.nz);
+    if (p.init_b)
+        r.init_b.assign(p.init_b, p.init_b + p.nz);
+    r.p.eps_rest = r.eps.data();
+    r.p.mu_rest = r.mu.data();
+    r.p.probe_cells = r.probes.data();
+    r.p.omegas = r.omegas.data();
+    r.p.init_d = p.init_d ? r.init_d.data() : nullptr;
+    r.p.init_b = p.init_b ? r.init_b.data() : nullptr;
+    return r;
+}
+
+hipError_t upload_run_inputs(char *base, const RunHost &r, hipStream_t stream)
+{
+    const size_t nz = (size_t)r.p.nz;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(base + r.L.eps, r.eps.data(), nz * 8, hipMemcpyHostToDevice, stream)) ||
+        (e = hipMemcpyAsync(base + r.L.mu, r.mu.data(), nz * 8, hipMemcpyHostToDevice, stream)))
+        return e;
+    if (r.p.nprobe &&
+        (e = hipMemcpyAsync(base + r.L.probes, r.probes.data(), r.probes.size() * 8,
+                            hipMemcpyHostToDevice, stream)))
+        return e;
+    if (r.p.nfreq &&
+        (e = hipMemcpyAsync(base + r.L.omegas, r.omegas.data(), r.omegas.size() * 8,
+                            hipMemcpyHostToDevice, stream)))
+        return e;
+    if (r.L.has_init_d &&
+        (e = hipMemcpyAsync(base + r.L.init_d, r.init_d.data(), nz * 8,
+                            hipMemcpyHostToDevice, stream)))
+        return e;
+    if (r.L.has_init_b &&
+        (e = hipMemcpyAsync(base + r.L.init_b, r.init_b.data(), nz * 8,
+                            hipMemcpyHostToDevice, stream)))
+        return e;
+    return hipSuccess;
 }
 
 size_t table_bytes(int nruns, int64_t max_tiles)
@@ -332,29 +391,20 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         st = preflight(&probs[i], nullptr);
         if (st != GFDTD_OK)
             return fail(st, "run %d: %s", i, last_error());
-        RunHost &r = runs[i];
-        r.p = probs[i];
-        r.steps = steps_in[i];
-        r.eps.assign(probs[i].eps_rest, probs[i].eps_rest + probs[i].nz);
-        r.mu.assign(probs[i].mu_rest, probs[i].mu_rest + probs[i].nz);
-        r.probes.assign(probs[i].probe_cells, probs[i].probe_cells + probs[i].nprobe);
-        r.omegas.assign(probs[i].omegas, probs[i].omegas + probs[i].nfreq);
-        r.p.eps_rest = r.eps.data();
-        r.p.mu_rest = r.mu.data();
-        r.p.probe_cells = r.probes.data();
-        r.p.omegas = r.omegas.data();
+        runs[i] = make_run_host(probs[i], steps_in[i]);
     }
-    // groups by (precision, kind)
+    // groups by (precision, kind, ring)
     Carver cv;
     for (auto &r : runs)
         carve_run(cv, &r.p, r.steps, r.L);
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
         Group G;
-        G.precision = g >> 1;
-        G.kind = g & 1;
+        G.precision = group_precision(g);
+        G.kind = group_kind(g);
+        G.ring = group_ring(g);
         int64_t max_steps = 0, cells = 0;
         for (int i = 0; i < count; ++i)
-            if (runs[i].p.precision == G.precision && runs[i].p.kind == G.kind) {
+            if (group_of(runs[i].p.precision, runs[i].p.kind, runs[i].p.abc) == g) {
                 G.members.push_back(i);
                 max_steps = std::max(max_steps, runs[i].steps);
                 cells += runs[i].p.nz;
@@ -378,20 +428,9 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
 
     hipError_t e;
     // uploads
-    for (auto &r : runs) {
-        const size_t nz = (size_t)r.p.nz;
-        if ((e = hipMemcpyAsync(ws + r.L.eps, r.eps.data(), nz * 8, hipMemcpyHostToDevice, stream)) ||
-            (e = hipMemcpyAsync(ws + r.L.mu, r.mu.data(), nz * 8, hipMemcpyHostToDevice, stream)))
-            return hip_fail(e, "upload rest profile");
-        if (r.p.nprobe &&
-            (e = hipMemcpyAsync(ws + r.L.probes, r.probes.data(), r.probes.size() * 8,
-                                hipMemcpyHostToDevice, stream)))
-            return hip_fail(e, "upload probes");
-        if (r.p.nfreq &&
-            (e = hipMemcpyAsync(ws + r.L.omegas, r.omegas.data(), r.omegas.size() * 8,
-                                hipMemcpyHostToDevice, stream)))
-            return hip_fail(e, "upload omegas");
-    }
+    for (auto &r : runs)
+        if ((e = upload_run_inputs(ws, r, stream)))
+            return hip_fail(e, "upload run inputs");
     // per-group descriptor tables
     for (auto &G : groups) {
         const int nr = (int)G.members.size();
@@ -402,6 +441,7 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         G.host_pd.assign(nr, PrepDesc{});
         G.host_dd.assign(nr, DftDesc{});
         G.max_cells = 0;
+        G.max_init = 0;
         G.max_field = 0;
         G.max_pf = 0;
         for (int m = 0; m < nr; ++m) {
@@ -409,6 +449,8 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
             RunDesc rd;
             fill_desc(r, G, 1, 1, kWave - 2, 0, rd, G.host_pd[m], G.host_dd[m]);
             G.max_cells = std::max<int64_t>(G.max_cells, std::max(r.p.nz, r.L.nsrc));
+            if (r.L.has_init_d || r.L.has_init_b)
+                G.max_init = std::max<int64_t>(G.max_init, r.p.nz);
             G.max_field = std::max<int64_t>(G.max_field, field_cells(r.p.nz));
             G.max_pf = std::max(G.max_pf, r.p.nprobe * r.p.nfreq);
         }
@@ -499,11 +541,11 @@ gfdtd_status Batch::build_tiles(Group &G)
 
 namespace {
 struct TuneKey {
-    int precision, kind, neg, runs_log2, cells_log2, steps_log2;
+    int group, neg, runs_log2, cells_log2, steps_log2;
     bool operator<(const TuneKey &o) const
     {
-        return std::tie(precision, kind, neg, runs_log2, cells_log2, steps_log2) <
-               std::tie(o.precision, o.kind, o.neg, o.runs_log2, o.cells_log2, o.steps_log2);
+        return std::tie(group, neg, runs_log2, cells_log2, steps_log2) <
+               std::tie(o.group, o.neg, o.runs_log2, o.cells_log2, o.steps_log2);
     }
 };
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;
@@ -533,8 +575,8 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
             steps = std::max(steps, (double)runs[i].steps);
             neg |= runs[i].p.beta < 0.0 ? 2 : 1;
         }
-        const TuneKey key{G.precision, G.kind, neg, ilog2((double)G.members.size()),
-                          ilog2(cells), ilog2(steps)};
+        const TuneKey key{G.precision * 4 + G.kind * 2 + (G.ring ? 1 : 0), neg,
+                          ilog2((double)G.members.size()), ilog2(cells), ilog2(steps)};
         {
             std::lock_guard<std::mutex> lk(g_tune_mutex);
             auto it = g_tune_cache.find(key);
@@ -576,7 +618,7 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                                (double)std::min<int64_t>(T, r.steps - b * (int64_t)T);
                     }
                 auto launch = [&](int64_t b) {
-                    return launch_tiles(G.precision, G.kind, C,
+                    return launch_tiles(G.precision, G.kind, G.ring, C,
                                         reinterpret_cast<const RunDesc *>(ws + G.runs_off),
                                         reinterpret_cast<const TileRef *>(ws + G.tiles_off),
                                         b, T, live_tiles(G, b), stream);
@@ -695,6 +737,7 @@ void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
     pd.phase = p.src_phase;
     pd.kind = p.kind;
     pd.precision = p.precision;
+    pd.abc = p.abc;
     pd.eps = reinterpret_cast<const double *>(base + r.L.eps);
     pd.mu = reinterpret_cast<const double *>(base + r.L.mu);
     pd.cE = base + r.L.cE;
@@ -708,6 +751,8 @@ void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
     pd.fields[2] = rd.B[0];
     pd.fields[3] = rd.B[1];
     pd.field_cells = field_cells(p.nz);
+    pd.init_d = r.L.has_init_d ? reinterpret_cast<const double *>(base + r.L.init_d) : nullptr;
+    pd.init_b = r.L.has_init_b ? reinterpret_cast<const double *>(base + r.L.init_b) : nullptr;
 
     std::memset(&dd, 0, sizeof dd);
     dd.steps = r.steps;
@@ -744,8 +789,10 @@ bool Batch::auto_graph() const
 gfdtd_status Batch::enqueue_zero(hipStream_t s)
 {
     for (auto &G : groups) {
-        hipError_t e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + G.prep_off),
-                                   (int)G.members.size(), G.max_field, G.precision, s);
+        const PrepDesc *pd = reinterpret_cast<const PrepDesc *>(ws + G.prep_off);
+        hipError_t e = launch_zero(pd, (int)G.members.size(), G.max_field, G.precision, s);
+        if (!e && G.max_init > 0)
+            e = launch_init(pd, (int)G.members.size(), G.max_init, G.precision, s);
         if (e)
             return hip_fail(e, "launch zero fill");
     }
@@ -761,7 +808,7 @@ gfdtd_status Batch::enqueue_steps(hipStream_t s)
         for (auto &G : groups) {
             if (b >= G.nblocks)
                 continue;
-            hipError_t e = launch_tiles(G.precision, G.kind, G.C,
+            hipError_t e = launch_tiles(G.precision, G.kind, G.ring, G.C,
                                         reinterpret_cast<const RunDesc *>(ws + G.runs_off),
                                         reinterpret_cast<const TileRef *>(ws + G.tiles_off),
                                         b, G.T, live_tiles(G, b), s);
@@ -839,6 +886,23 @@ gfdtd_status Batch::run()
     return GFDTD_OK;
 }
 
+void initial_fields(const RunHost &r, double *d, double *b)
+{
+    const int64_t nz = r.p.nz;
+    const bool f32 = r.p.precision == GFDTD_F32;
+    const bool ring = r.p.abc == GFDTD_ABC_PERIODIC;
+    auto fill = [&](const std::vector<double> &src, double *dst, int64_t n) {
+        for (int64_t i = 0; i < nz; ++i) {
+            const double v = (i < n && !src.empty()) ? src[i] : 0.0;
+            dst[i] = f32 ? (double)(float)v : v;
+        }
+    };
+    if (d)
+        fill(r.init_d, d, nz);
+    if (b)
+        fill(r.init_b, b, ring ? nz : nz - 1);
+}
+
 gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *out_in,
                           hipStream_t stream, gfdtd_result *out)
 {
@@ -894,16 +958,15 @@ gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *
                             : reinterpret_cast<const double *>(src.data())[i];
     };
     if (r.steps == 0) {
-        if (out->final_d)
-            std::memset(out->final_d, 0, (size_t)p.nz * 8);
-        if (out->final_b)
-            std::memset(out->final_b, 0, (size_t)p.nz * 8);
+        initial_fields(r, out->final_d, out->final_b);
     } else {
         if (out->final_d)
             conv(fd, out->final_d, p.nz);
         if (out->final_b) {
-            conv(fb, out->final_b, p.nz - 1);
-            out->final_b[p.nz - 1] = 0.0;
+            const bool ring = p.abc == GFDTD_ABC_PERIODIC;
+            conv(fb, out->final_b, ring ? p.nz : p.nz - 1);
+            if (!ring)
+                out->final_b[p.nz - 1] = 0.0;
         }
     }
     return GFDTD_OK;
@@ -1019,19 +1082,19 @@ gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
     if (!bytes || count < 0 || (count > 0 && (!probs || !steps)))
         return fail(GFDTD_E_INVALID, "bad arguments");
     Carver cv;
-    int64_t maxt[4] = {0, 0, 0, 0};
-    int nr[4] = {0, 0, 0, 0};
+    int64_t maxt[kGroups] = {};
+    int nr[kGroups] = {};
     for (int i = 0; i < count; ++i) {
         gfdtd_status st = validate(&probs[i], steps[i]);
         if (st != GFDTD_OK)
             return fail(st, "run %d: %s", i, last_error());
         RunLayout L;
         carve_run(cv, &probs[i], steps[i], L);
-        const int g = probs[i].precision * 2 + probs[i].kind;
+        const int g = group_of(probs[i].precision, probs[i].kind, probs[i].abc);
         maxt[g] += max_tiles_of(probs[i].nz);
         nr[g] += 1;
     }
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < kGroups; ++g)
         if (nr[g])
             cv.take(table_bytes(nr[g], maxt[g]));
     *bytes = cv.off;

@@ -31,6 +31,8 @@ struct RunLayout {
     size_t eps = 0, mu = 0, cE = 0, cH = 0, gB = 0, murL = 0, murR = 0;
     size_t src = 0, probes = 0, omegas = 0, trace = 0, dft = 0;
     size_t field[4] = {0, 0, 0, 0};   // D0, D1, B0, B1 (padded)
+    size_t init_d = 0, init_b = 0;    // FP64 initial fields, if given
+    bool has_init_d = false, has_init_b = false;
     int64_t nsrc = 0;
 };
 
@@ -48,14 +50,24 @@ struct RunHost {
     gfdtd_problem p{};
     int64_t steps = 0;
     int T = 1;                  // block depth of its group
-    std::vector<double> eps, mu, omegas;
+    std::vector<double> eps, mu, omegas, init_d, init_b;
     std::vector<int64_t> probes;
     RunLayout L;
 };
 
+// Host copies of a (validated) problem's inputs; r.p points into them.
+RunHost make_run_host(const gfdtd_problem &p, int64_t steps);
+// Asynchronous uploads of a carved run's inputs (rest profile, probes,
+// frequencies, initial fields) into the workspace at base.
+hipError_t upload_run_inputs(char *base, const RunHost &r, hipStream_t stream);
+
 void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
                    int64_t own, int64_t start_block, RunDesc &rd, PrepDesc &pd,
                    DftDesc &dd);
+
+// The state a run of zero steps returns: its initial fields (or zeros),
+// rounded to the run precision; either pointer may be null.
+void initial_fields(const RunHost &r, double *d, double *b);
 
 gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *unused,
                           hipStream_t stream, gfdtd_result *out);
@@ -63,11 +75,12 @@ gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *
 // Runs of one precision and kind, stepped by one kernel instantiation.
 struct Group {
     int precision = 0, kind = 0, C = 16, T = 16;
+    bool ring = false;                // periodic ends
     std::vector<int> members;         // run indices, longest first
     std::vector<int64_t> blocks_of;   // blocks per member
     std::vector<int64_t> tiles_prefix;
     int64_t nblocks = 0;
-    int64_t max_cells = 0, max_field = 0;
+    int64_t max_cells = 0, max_field = 0, max_init = 0;
     int max_pf = 0;
     size_t table_off = 0, runs_off = 0, tiles_off = 0, prep_off = 0, dft_off = 0;
     std::vector<RunDesc> host_rd;

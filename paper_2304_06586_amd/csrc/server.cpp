@@ -3,10 +3,10 @@
 // Requests wait in a FIFO queue until their device state fits in the pool
 // (the caller's HBM budget) and a slot is free.  Admitted runs share
 // progress blocks: one block advances every admitted run by T steps with
-// one k_tiles launch per (precision, kind) group.
+// one k_tiles launch per (precision, kind, ring) group.
 //
-// Each (precision, kind) group runs on a stream of its own, so launches of
-// different groups overlap; they fork from the caller's stream at every
+// Each (precision, kind) pair runs on a stream of its own, so launches of
+// different pairs overlap; they fork from the caller's stream at every
 // progress call.  Everything is stream-ordered, so the host never waits for
 // the GPU in steady state:
 //  - admission copies a request's inputs into a pinned host buffer, then
@@ -158,7 +158,7 @@ struct Request {
     State state = QUEUED;
     size_t off = 0, bytes = 0;       // pool region
     size_t desc_off = 0;             // RunDesc, PrepDesc, DftDesc of the run
-    int group = 0;                   // precision * 2 + kind
+    int group = 0;                   // group_of(precision, kind, abc)
     int hl = 0, hr = 0;
     int64_t own = 0, ntiles = 0;
     int64_t start_block = 0, end_block = 0;
@@ -184,11 +184,11 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Server {
     hipStream_t stream = nullptr;    // the caller's stream
-    hipStream_t gs[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t gs[4] = {nullptr, nullptr, nullptr, nullptr};   // by g >> 1
     hipEvent_t fork_ev = nullptr;
     // per group: retirements (releases of pool memory) its stream has not
     // yet been ordered after
-    std::vector<std::shared_ptr<void>> released[4];
+    std::vector<std::shared_ptr<void>> released[kGroups];
     PinnedPool pins;
     char *pool_base = nullptr;
     size_t pool_bytes = 0;
@@ -203,13 +203,13 @@ struct Server {
     std::deque<uint64_t> queue;
     std::vector<uint64_t> live;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-    bool gdirty[4] = {true, true, true, true};
-    int cur[4] = {0, 0, 0, 0};       // table buffer in use, per group
-    size_t runs_off[2][4], tiles_off[2][4];
-    int ntiles[4] = {0, 0, 0, 0};
-    Pinned stage[2][4];              // host staging of the table buffers
-    hipEvent_t stage_ev[2][4] = {};
-    bool stage_used[2][4] = {};
+    bool gdirty[kGroups] = {true, true, true, true, true, true, true, true};
+    int cur[kGroups] = {};           // table buffer in use, per group
+    size_t runs_off[2][kGroups], tiles_off[2][kGroups];
+    int ntiles[kGroups] = {};
+    Pinned stage[2][kGroups];        // host staging of the table buffers
+    hipEvent_t stage_ev[2][kGroups] = {};
+    bool stage_used[2][kGroups] = {};
 
     ~Server()
     {
@@ -255,7 +255,7 @@ struct Server {
         tile_cap = (int64_t)(pool_bytes / (64 * 32)) + 8 * (int64_t)max_slots;
         Carver cv;
         for (int k = 0; k < 2; ++k)
-            for (int g = 0; g < 4; ++g) {
+            for (int g = 0; g < kGroups; ++g) {
                 runs_off[k][g] = cv.take((size_t)max_slots * sizeof(RunDesc));
                 tiles_off[k][g] = cv.take((size_t)tile_cap * sizeof(TileRef));
             }
@@ -266,7 +266,7 @@ struct Server {
         pool.init(pool_bytes - tables_bytes);
         hipError_t e;
         for (int k = 0; k < 2; ++k)
-            for (int g = 0; g < 4; ++g)
+            for (int g = 0; g < kGroups; ++g)
                 if ((e = hipEventCreateWithFlags(&stage_ev[k][g], hipEventDisableTiming)))
                     return hip_fail(e, "create events");
         for (int g = 0; g < 4; ++g)
@@ -296,22 +296,13 @@ struct Server {
             return st;
         std::unique_ptr<Request> rq(new Request);
         RunHost &r = rq->r;
-        r.p = *p;
-        r.steps = steps;
+        r = make_run_host(*p, steps);
         r.T = T;
-        r.eps.assign(p->eps_rest, p->eps_rest + p->nz);
-        r.mu.assign(p->mu_rest, p->mu_rest + p->nz);
-        r.probes.assign(p->probe_cells, p->probe_cells + p->nprobe);
-        r.omegas.assign(p->omegas, p->omegas + p->nfreq);
-        r.p.eps_rest = r.eps.data();
-        r.p.mu_rest = r.mu.data();
-        r.p.probe_cells = r.probes.data();
-        r.p.omegas = r.omegas.data();
         rq->bytes = footprint(&r.p, steps, r.L, rq->desc_off);
         if (rq->bytes > pool.size)
             return fail(GFDTD_E_NOMEM, "request needs %zu bytes, pool holds %zu",
                         rq->bytes, pool.size);
-        rq->group = p->precision * 2 + p->kind;
+        rq->group = group_of(p->precision, p->kind, p->abc);
         if (!halo_lanes(p->beta, Cg[p->precision], T, rq->hl, rq->hr))
             return fail(GFDTD_E_INVALID, "block depth too large");
         rq->own = (int64_t)(kWave - rq->hl - rq->hr) * Cg[p->precision];
@@ -342,7 +333,8 @@ struct Server {
             RunLayout &L = rq->r.L;
             size_t *fields[] = {&L.eps, &L.mu, &L.cE, &L.cH, &L.gB, &L.murL, &L.murR,
                                 &L.src, &L.probes, &L.omegas, &L.trace, &L.dft,
-                                &L.field[0], &L.field[1], &L.field[2], &L.field[3]};
+                                &L.field[0], &L.field[1], &L.field[2], &L.field[3],
+                                &L.init_d, &L.init_b};
             for (size_t *f : fields)
                 *f += rq->off;
             rq->desc_off += rq->off;
@@ -352,7 +344,7 @@ struct Server {
             live.push_back(rq->id);
             ntiles[rq->group] += (int)rq->ntiles;
             gdirty[rq->group] = true;
-            hipStream_t st = gs[rq->group];
+            hipStream_t st = gs[rq->group >> 1];
             // memory released by retirements on other streams is reused
             // only after those retirements
             for (auto &ev : released[rq->group])
@@ -370,6 +362,8 @@ struct Server {
             const size_t h_mu = o;   o += align256(nz * 8);
             const size_t h_pr = o;   o += align256(std::max<size_t>(r.probes.size(), 1) * 8);
             const size_t h_om = o;   o += align256(std::max<size_t>(r.omegas.size(), 1) * 8);
+            const size_t h_id = o;   o += L.has_init_d ? align256(nz * 8) : 0;
+            const size_t h_ib = o;   o += L.has_init_b ? align256(nz * 8) : 0;
             const size_t h_desc = o; o += align256(sizeof(RunDesc) + sizeof(PrepDesc) +
                                                    sizeof(DftDesc));
             rq->h_dft = o;   o += align256((size_t)std::max(p.nprobe * p.nfreq, 1) * 16);
@@ -393,6 +387,10 @@ struct Server {
                 std::memcpy(h + h_pr, r.probes.data(), r.probes.size() * 8);
             if (!r.omegas.empty())
                 std::memcpy(h + h_om, r.omegas.data(), r.omegas.size() * 8);
+            if (L.has_init_d)
+                std::memcpy(h + h_id, r.init_d.data(), nz * 8);
+            if (L.has_init_b)
+                std::memcpy(h + h_ib, r.init_b.data(), nz * 8);
             RunDesc rd;
             PrepDesc pd;
             DftDesc dd;
@@ -417,11 +415,20 @@ struct Server {
                 (e = hipMemcpyAsync(pool_base + L.omegas, h + h_om, r.omegas.size() * 8,
                                     hipMemcpyHostToDevice, st)))
                 return hip_fail(e, "upload omegas");
+            if ((L.has_init_d &&
+                 (e = hipMemcpyAsync(pool_base + L.init_d, h + h_id, nz * 8,
+                                     hipMemcpyHostToDevice, st))) ||
+                (L.has_init_b &&
+                 (e = hipMemcpyAsync(pool_base + L.init_b, h + h_ib, nz * 8,
+                                     hipMemcpyHostToDevice, st))))
+                return hip_fail(e, "upload initial fields");
             const PrepDesc *dp =
                 reinterpret_cast<const PrepDesc *>(pool_base + rq->desc_off + sizeof(RunDesc));
             if ((e = launch_prep(dp, 1, (int)std::min<int64_t>(std::max(p.nz, L.nsrc), 1 << 30),
                                  st)) ||
-                (e = launch_zero(dp, 1, field_cells(p.nz), p.precision, st)))
+                (e = launch_zero(dp, 1, field_cells(p.nz), p.precision, st)) ||
+                ((L.has_init_d || L.has_init_b) &&
+                 (e = launch_init(dp, 1, p.nz, p.precision, st))))
                 return hip_fail(e, "launch set-up");
         }
         return GFDTD_OK;
@@ -464,11 +471,12 @@ struct Server {
         char *h = static_cast<char *>(stage[nxt][g].p);
         std::memcpy(h, rd.data(), a);
         std::memcpy(h + align256(a), tl.data(), b);
+        hipStream_t gst = gs[g >> 1];
         if ((e = hipMemcpyAsync(pool_base + runs_off[nxt][g], h, a, hipMemcpyHostToDevice,
-                                gs[g])) ||
+                                gst)) ||
             (e = hipMemcpyAsync(pool_base + tiles_off[nxt][g], h + align256(a), b,
-                                hipMemcpyHostToDevice, gs[g])) ||
-            (e = hipEventRecord(stage_ev[nxt][g], gs[g])))
+                                hipMemcpyHostToDevice, gst)) ||
+            (e = hipEventRecord(stage_ev[nxt][g], gst)))
             return hip_fail(e, "upload tables");
         stage_used[nxt][g] = true;
         return GFDTD_OK;
@@ -482,7 +490,7 @@ struct Server {
         const gfdtd_problem &p = rq->r.p;
         const RunLayout &L = rq->r.L;
         char *h = static_cast<char *>(rq->host);
-        hipStream_t stream = gs[rq->group];
+        hipStream_t stream = gs[rq->group >> 1];
         const DftDesc *dd = reinterpret_cast<const DftDesc *>(
             pool_base + rq->desc_off + sizeof(RunDesc) + sizeof(PrepDesc));
         if ((e = launch_dft(dd, 1, p.nprobe * p.nfreq, stream)))
@@ -518,8 +526,8 @@ struct Server {
         std::shared_ptr<void> ev(rel, [](void *x) {
             (void)hipEventDestroy(static_cast<hipEvent_t>(x));
         });
-        for (int g = 0; g < 4; ++g)
-            if (g != rq->group)
+        for (int g = 0; g < kGroups; ++g)
+            if ((g >> 1) != (rq->group >> 1))
                 released[g].push_back(ev);
         rq->state = RETIRING;
         pool.release(rq->off - tables_bytes, rq->bytes);
@@ -558,7 +566,7 @@ struct Server {
                 continue;
             if (live.empty() || left <= 0)
                 break;
-            for (int g = 0; g < 4; ++g)
+            for (int g = 0; g < kGroups; ++g)
                 if (gdirty[g] && (st = rebuild_tables(g)) != GFDTD_OK)
                     return st;
             int64_t next_end = INT64_MAX;
@@ -566,13 +574,14 @@ struct Server {
                 next_end = std::min(next_end, reqs[id]->end_block);
             const int64_t nb = std::min<int64_t>(next_end - gblock + 1, left);
             for (int64_t b = 0; b < nb; ++b, ++gblock)
-                for (int g = 0; g < 4; ++g) {
+                for (int g = 0; g < kGroups; ++g) {
                     if (!ntiles[g])
                         continue;
-                    e = launch_tiles(g >> 1, g & 1, Cg[g >> 1],
+                    const int pr = group_precision(g);
+                    e = launch_tiles(pr, group_kind(g), group_ring(g), Cg[pr],
                                      reinterpret_cast<const RunDesc *>(pool_base + runs_off[cur[g]][g]),
                                      reinterpret_cast<const TileRef *>(pool_base + tiles_off[cur[g]][g]),
-                                     gblock, T, ntiles[g], gs[g]);
+                                     gblock, T, ntiles[g], gs[g >> 1]);
                     if (e)
                         return hip_fail(e, "launch step kernel");
                 }
@@ -642,15 +651,20 @@ struct Server {
         const bool f32 = p.precision == GFDTD_F32;
         auto field = [&](size_t o, double *dst, int64_t n) {
             for (int64_t i = 0; i < n; ++i)
-                dst[i] = rq->r.steps == 0 ? 0.0
-                         : f32 ? (double)reinterpret_cast<const float *>(h + o)[i]
-                               : reinterpret_cast<const double *>(h + o)[i];
+                dst[i] = f32 ? (double)reinterpret_cast<const float *>(h + o)[i]
+                             : reinterpret_cast<const double *>(h + o)[i];
         };
-        if (out->final_d && keep)
-            field(rq->h_d, out->final_d, p.nz);
-        if (out->final_b && keep) {
-            field(rq->h_b, out->final_b, p.nz - 1);
-            out->final_b[p.nz - 1] = 0.0;
+        if (keep && rq->r.steps == 0) {
+            initial_fields(rq->r, out->final_d, out->final_b);
+        } else if (keep) {
+            const bool ring = p.abc == GFDTD_ABC_PERIODIC;
+            if (out->final_d)
+                field(rq->h_d, out->final_d, p.nz);
+            if (out->final_b) {
+                field(rq->h_b, out->final_b, ring ? p.nz : p.nz - 1);
+                if (!ring)
+                    out->final_b[p.nz - 1] = 0.0;
+            }
         }
         reqs.erase(it);
         return GFDTD_OK;

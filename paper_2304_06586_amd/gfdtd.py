@@ -8,7 +8,7 @@ path: if the native library is missing the calls raise.
 Problem descriptors are duck-typed: any object with the attributes of
 `workloads.Problem` (nz, steps, courant, beta, kind, precision, abc,
 flags, eps_rest, mu_rest, src_cell, pulse.{amp, omega, t0, tau, phase,
-t_off}, probes, omegas).
+t_off}, probes, omegas, and optionally init_d / init_b).
 """
 from __future__ import annotations
 
@@ -37,6 +37,7 @@ GFDTD_F32 = 0
 GFDTD_F64 = 1
 GFDTD_ABC_MUR1 = 0
 GFDTD_ABC_PEC = 1
+GFDTD_ABC_PERIODIC = 2
 GFDTD_FLAG_RECORD_TRACE = 1
 GFDTD_FLAG_ALLOW_UNSTABLE = 2
 GFDTD_FLAG_KEEP_FIELDS = 4
@@ -59,6 +60,7 @@ class gfdtd_problem(C.Structure):
         ("src_t0", C.c_double), ("src_tau", C.c_double),
         ("src_phase", C.c_double), ("src_t_off", C.c_double),
         ("probe_cells", _PI64), ("omegas", _PD),
+        ("init_d", _PD), ("init_b", _PD),
     ]
 
 
@@ -204,6 +206,17 @@ class _Marshalled:
         s.src_t_off = float(p.pulse.t_off)
         s.probe_cells = self.probes.ctypes.data_as(_PI64) if self.nprobe else None
         s.omegas = self.omegas.ctypes.data_as(_PD) if self.nfreq else None
+        self.init = []
+        for name in ("init_d", "init_b"):
+            a = getattr(p, name, None)
+            if a is not None:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                if a.shape != (self.nz,):
+                    raise ValueError(f"{name} must hold nz = {self.nz} values")
+                self.init.append(a)
+                setattr(s, name, a.ctypes.data_as(_PD))
+            else:
+                setattr(s, name, None)
         self.struct = s
 
 

@@ -1,0 +1,189 @@
+"""GPU parity for periodic ends (rings), initial fields and the stability /
+dispersion sweep (Section 5, Fig. 4): the HIP path through the C-ABI
+against the FP64 oracle on the same seeded inputs, and the sweep's
+amplification factors against the oracle's von Neumann matrix G.
+
+Tolerances as in test_gpu_parity: relative L2 1e-12 (FP64), 1e-4 (FP32).
+The sweep compares |zeta| per point: 1e-10 in FP64; in FP32 the fields
+carry ~1e-7 relative rounding per step, so 2e-5 over 16 steps."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from oracle import stability as st
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-4
+
+
+def rel(a, b):
+    den = np.linalg.norm(np.ravel(b))
+    num = np.linalg.norm(np.ravel(a) - np.ravel(b))
+    return float(num / den) if den > 0 else float(num)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2304_06586_amd as pkg
+    pkg.load_library()
+    return pkg
+
+
+def compare(got, want, tol, label, ring=True):
+    errs = {}
+    for key in ("trace", "dft", "d", "b"):
+        a, b = got[key], want[key]
+        if key == "b" and not ring:
+            a, b = a[:-1], b[:-1]
+        if np.size(b) == 0:
+            continue
+        errs[key] = rel(a, b)
+    print(f"{label}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for k, v in errs.items():
+        assert v <= tol, (label, k, v)
+    assert got["status"] == 0
+
+
+RING_CASES = [
+    # nz, steps, beta, kind, structure
+    (8, 40, 0.3, W.MODULATION, "uniform"),
+    (13, 77, -0.25, W.MODULATION, "random"),
+    (100, 300, 0.4, W.MODULATION, "slab"),
+    (517, 333, -0.35, W.MODULATION, "crystal"),
+    (3001, 900, 0.3, W.MODULATION, "random"),
+    (64, 200, 0.25, W.MATTER, "random"),
+    (2049, 500, -0.3, W.MATTER, "slab"),
+]
+
+
+@pytest.mark.parametrize("nz,steps,beta,kind,structure", RING_CASES)
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_ring_with_source_probes_and_initial_fields(P, nz, steps, beta, kind,
+                                                    structure, precision):
+    """Rings shorter than, equal to and longer than a tile, the moving
+    profile wrapping around, a source, probes and a random initial state."""
+    p = W.small_case(nz, steps, beta, kind=kind, structure=structure,
+                     precision=precision, seed=nz + 7, abc=W.ABC_PERIODIC, nprobe=4)
+    d, b = W.random_fields(nz, seed=nz)
+    p = p.replace(init_d=d, init_b=b)
+    tol = TOL64 if precision == W.F64 else TOL32
+    compare(P.gfdtd_solve(p), oracle.solve(p), tol,
+            f"ring {nz}x{steps} b={beta} k={kind} p={precision}")
+
+
+@pytest.mark.parametrize("C,T", [(4, 1), (8, 24), (16, 33), (4, 7)])
+@pytest.mark.parametrize("nz", [9, 700, 2345])
+def test_ring_tilings_agree_bitwise(P, C, T, nz):
+    p = W.small_case(nz, 211, 0.35, structure="crystal", seed=5, nprobe=3,
+                     abc=W.ABC_PERIODIC)
+    p = p.replace(src_cell=0)
+
+    def run(c, t):
+        with P.Batch([p], cells_per_lane=c, block_steps=t, use_graph=0) as bt:
+            bt.run()
+            return bt.collect()[0]
+
+    ref = run(8, 1)
+    out = run(C, T)
+    for k in ("trace", "dft", "d", "b"):
+        assert np.array_equal(out[k], ref[k]), (C, T, k)
+    compare(out, oracle.solve(p), TOL64, f"ring tiling C={C} T={T} nz={nz}")
+
+
+@pytest.mark.parametrize("beta", [0.3, -0.3])
+@pytest.mark.parametrize("kind", [W.MODULATION, W.MATTER])
+def test_initial_fields_with_absorbing_ends(P, beta, kind):
+    p = W.small_case(1800, 600, beta, kind=kind, structure="slab", seed=21)
+    d, b = W.random_fields(1800, seed=3)
+    p = p.replace(init_d=d, init_b=b)
+    compare(P.gfdtd_solve(p), oracle.solve(p), TOL64, f"init mur b={beta} k={kind}",
+            ring=False)
+
+
+def test_zero_steps_return_the_initial_state(P):
+    d, b = W.random_fields(300, seed=8)
+    for abc in (W.ABC_MUR1, W.ABC_PERIODIC):
+        for prec, cast in ((W.F64, np.float64), (W.F32, np.float32)):
+            p = W.small_case(300, 0, 0.3, seed=2, abc=abc, precision=prec)
+            got = P.gfdtd_solve(p.replace(init_d=d, init_b=b))
+            assert np.array_equal(got["d"], d.astype(cast).astype(np.float64))
+            nb = 300 if abc == W.ABC_PERIODIC else 299
+            assert np.array_equal(got["b"][:nb], b[:nb].astype(cast).astype(np.float64))
+
+
+def _zeta_table(points):
+    return np.array([[abs(z) for z in st.zetas(p.theta, p.courant, p.beta, p.eps,
+                                                p.mu, p.kind)] for p in points])
+
+
+@pytest.mark.parametrize("precision,tol,min_ratio", [(W.F64, 1e-9, 1e-6),
+                                                     (W.F32, 2e-5, 1e-2)])
+def test_dispersion_sweep_matches_amplification_matrix(P, precision, tol, min_ratio):
+    """One batch: the Fig. 4 setting (S = 0.5, beta = 0.3, eps = 4) over 89
+    meshing densities plus 1024 random (S, beta, eps, N_lambda) points,
+    two ring runs each, 8 steps; |zeta_+|, |zeta_-| read off the GPU
+    fields against eig G.  Every Fig. 4 point must resolve both modes;
+    of the random points at most 2 % may leave a strongly damped mode
+    unresolved (it is then NaN, never a wrong number)."""
+    from paper_2304_06586_amd import dispersion as DS
+    fig4 = W.fig4_points(max_nz=24)
+    pts = fig4 + W.dispersion_points(7, 1024, max_nz=256)
+    steps = 8
+    runs = W.dispersion_runs(pts, steps, precision=precision)
+    res = P.gfdtd_solve_batch(runs)
+    assert all(r["status"] == 0 for r in res)
+    got = DS.sweep_growth(pts, res, steps, min_ratio=min_ratio)
+    want = _zeta_table(pts)
+    ok = ~np.isnan(got)
+    assert ok[:len(fig4)].all()
+    assert ok.mean() > 0.98
+    err = np.max(np.abs(got[ok] - want[ok]))
+    print(f"sweep precision={precision}: max |zeta| error {err:.2e} over "
+          f"{len(pts)} points, {int((~ok).sum())} modes unresolved", flush=True)
+    assert err < tol
+    # the printed worked example (N_lambda = 5): 0.98 and 0.95
+    i = [k for k, p in enumerate(pts) if p.nz == 10 and p.m == 2][0]
+    assert round(got[i, 0], 2) == 0.98 and round(got[i, 1], 2) == 0.95
+    # fields of a sample of runs against the oracle
+    for j in (0, 1, 2 * i, 2 * i + 1, len(runs) - 1):
+        tolf = TOL64 if precision == W.F64 else TOL32
+        want_f = oracle.solve(runs[j])
+        assert rel(res[j]["d"], want_f["d"]) < tolf
+        assert rel(res[j]["b"], want_f["b"]) < tolf
+
+
+def test_server_rings_and_initial_fields_equal_alone(P):
+    """Ring and initial-field requests mixed with ordinary ones in the
+    continuous-batching server give the same bits as alone."""
+    probs = []
+    for i in range(8):
+        abc = W.ABC_PERIODIC if i % 2 == 0 else W.ABC_MUR1
+        p = W.small_case(300 + 97 * i, 150 + 31 * i, 0.3 if i % 3 else -0.25,
+                         abc=abc, seed=40 + i, nprobe=3,
+                         precision=W.F64 if i < 5 else W.F32)
+        if i % 4 != 3:
+            d, b = W.random_fields(p.nz, seed=i)
+            p = p.replace(init_d=d, init_b=b)
+        probs.append(p)
+    alone = [P.gfdtd_solve(p) for p in probs]
+    with P.Server(pool_bytes=256 << 20, max_slots=8, block_steps=16) as srv:
+        ids = [srv.submit(p, record_trace=True, keep_fields=True) for p in probs]
+        done = {}
+        for _ in range(100000):
+            srv.progress(max_blocks=4)
+            for i, rid in enumerate(ids):
+                if i not in done:
+                    r = srv.poll(rid)
+                    if r is not None:
+                        done[i] = r
+            if len(done) == len(ids):
+                break
+    assert len(done) == len(ids)
+    for i in range(len(probs)):
+        for k in ("trace", "dft", "d", "b"):
+            assert np.array_equal(done[i][k], alone[i][k]), (i, k)

@@ -50,7 +50,7 @@ def test_struct_sizes_match_header(P):
     """The ctypes layouts match the C structs (the library rejects a
     smaller struct_size, so a mismatch would show as E_INVALID)."""
     g = P.gfdtd
-    assert ctypes.sizeof(g.gfdtd_problem) == 4 * 8 + 8 * 3 + 8 * 2 + 8 + 6 * 8 + 8 * 2
+    assert ctypes.sizeof(g.gfdtd_problem) == 4 * 8 + 8 * 3 + 8 * 2 + 8 + 6 * 8 + 8 * 4
     assert ctypes.sizeof(g.gfdtd_result) == 8 + 8 + 5 * 8
     assert ctypes.sizeof(g.gfdtd_exec) == 24
     assert ctypes.sizeof(g.gfdtd_stats) == 16 + 16 + 24
@@ -98,10 +98,29 @@ def test_invalid_arrays_rejected(P):
         P.gfdtd_check(p.replace(mu_rest=nan))
 
 
-def test_periodic_ends_unsupported(P):
+def test_periodic_ends_and_initial_fields_validated(P):
+    """A ring accepts a source at any cell (0..nz-1); a grid with ends
+    only at 1..nz-2.  Initial fields must be finite and nz long."""
+    ring = _ok().replace(abc=W.ABC_PERIODIC)
+    for cell in (0, 199):
+        P.gfdtd_check(ring.replace(src_cell=cell))
+        with pytest.raises(P.GfdtdError) as e:
+            P.gfdtd_check(_ok().replace(src_cell=cell))
+        assert e.value.status == P.gfdtd.GFDTD_E_INVALID
     with pytest.raises(P.GfdtdError) as e:
-        P.gfdtd_check(_ok().replace(abc=W.ABC_PERIODIC))
-    assert e.value.status == P.gfdtd.GFDTD_E_UNSUPPORTED
+        P.gfdtd_check(ring.replace(src_cell=200))
+    assert e.value.status == P.gfdtd.GFDTD_E_INVALID
+    d, b = W.random_fields(200, 1)
+    P.gfdtd_check(ring.replace(init_d=d, init_b=b))
+    P.gfdtd_check(_ok().replace(init_b=b))
+    bad = d.copy()
+    bad[57] = float("nan")
+    for q in (ring.replace(init_d=bad), _ok().replace(init_b=bad)):
+        with pytest.raises(P.GfdtdError) as e:
+            P.gfdtd_check(q)
+        assert e.value.status == P.gfdtd.GFDTD_E_INVALID
+    with pytest.raises(ValueError):
+        P.gfdtd_check(ring.replace(init_d=d[:-1]))
 
 
 @pytest.mark.parametrize("kind", [W.MODULATION, W.MATTER])

@@ -30,7 +30,7 @@ F32 = 0
 F64 = 1
 ABC_MUR1 = 0        # first-order absorbing ends
 ABC_PEC = 1         # D = 0 at both end nodes
-ABC_PERIODIC = 2    # ring grid (used by the von Neumann checks)
+ABC_PERIODIC = 2    # ring grid: node nz-1 next to node 0
 
 FLAG_RECORD_TRACE = 1
 FLAG_ALLOW_UNSTABLE = 2
@@ -99,12 +99,20 @@ class Problem:
     abc: int = ABC_MUR1
     flags: int = 0
     label: str = ""
+    # initial state: D at t = S/2 and B at t = 0 (nz values each; on a grid
+    # with ends the last B entry is unused); None means zero
+    init_d: Optional[np.ndarray] = None
+    init_b: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.eps_rest = np.ascontiguousarray(self.eps_rest, dtype=np.float64)
         self.mu_rest = np.ascontiguousarray(self.mu_rest, dtype=np.float64)
         self.probes = np.ascontiguousarray(self.probes, dtype=np.int64)
         self.omegas = np.ascontiguousarray(self.omegas, dtype=np.float64)
+        if self.init_d is not None:
+            self.init_d = np.ascontiguousarray(self.init_d, dtype=np.float64)
+        if self.init_b is not None:
+            self.init_b = np.ascontiguousarray(self.init_b, dtype=np.float64)
 
     @property
     def cell_updates(self) -> int:
@@ -367,3 +375,106 @@ def small_case(nz: int, steps: int, beta: float, kind: int = MODULATION,
                    src_cell=src, pulse=pulse, probes=probes,
                    omegas=default_omegas(pulse.omega, nfreq), abc=abc,
                    label=f"small_{structure}")
+
+
+def random_fields(nz: int, seed: int, scale: float = 1.0
+                  ) -> Tuple[np.ndarray, np.ndarray]:
+    """Seeded smooth random initial fields (D, B): a sum of a few long
+    waves plus small white noise, for runs that start from a non-zero
+    state."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(nz, dtype=np.float64)
+    d = np.zeros(nz)
+    b = np.zeros(nz)
+    for _ in range(4):
+        kz = 2.0 * math.pi * rng.uniform(0.005, 0.2)
+        d += rng.normal() * np.cos(kz * k + rng.uniform(0, 2 * math.pi))
+        b += rng.normal() * np.cos(kz * (k + 0.5) + rng.uniform(0, 2 * math.pi))
+    d += 0.05 * rng.normal(size=nz)
+    b += 0.05 * rng.normal(size=nz)
+    return scale * d, scale * b
+
+
+# --------------------------------------------------------------------------
+# Plane waves on rings: the stability / dispersion sweep (Section 5, Fig. 4)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class DispersionPoint:
+    """One point of the sweep: a uniform medium (eps' = eps, mu' = mu) on a
+    ring of nz cells moving at beta, time step S, and the plane wave with
+    m wavelengths around the ring, k_z dz = 2 pi m / nz, i.e. a meshing
+    density N_lambda = nz / m cells per wavelength."""
+    courant: float
+    beta: float
+    eps: float
+    nz: int
+    m: int
+    mu: float = 1.0
+    kind: int = MODULATION
+
+    @property
+    def theta(self) -> float:
+        return 2.0 * math.pi * self.m / self.nz
+
+    @property
+    def n_lambda(self) -> float:
+        return self.nz / self.m
+
+
+def fig4_points(courant: float = 0.5, beta: float = 0.3, eps: float = 4.0,
+                max_nz: int = 64) -> List[DispersionPoint]:
+    """The setting of the paper's stability figure: S = 0.5, beta = 0.3,
+    eps = 4, mu = 1, swept over meshing densities N_lambda = nz/m on rings
+    of 8..max_nz cells (one point per distinct N_lambda, m < nz/2)."""
+    seen = {}
+    for nz in range(8, max_nz + 1):
+        for m in range(1, (nz - 1) // 2 + 1):
+            key = round(nz / m, 9)
+            if key not in seen:
+                seen[key] = DispersionPoint(courant, beta, eps, nz, m)
+    return [seen[k] for k in sorted(seen)]
+
+
+def dispersion_points(seed: int, count: int, max_nz: int = 256,
+                      kinds=(MODULATION,)) -> List[DispersionPoint]:
+    """Seeded random sweep points.  Drawn in order: S ~ U[0.05, 0.95],
+    eps ~ U[1, 9], beta ~ U[-0.9, 0.9], nz ~ U{8..max_nz}, m ~
+    U{1..(nz-1)//2}, kind uniform over `kinds`; a draw is repeated while
+    |beta| n > 0.98 or S > 0.98 n / (1 + n |beta|) (n = sqrt(eps)), the
+    luminal and Courant-type limits the stability analysis gives."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        S = float(rng.uniform(0.05, 0.95))
+        eps = float(rng.uniform(1.0, 9.0))
+        beta = float(rng.uniform(-0.9, 0.9))
+        nz = int(rng.integers(8, max_nz + 1))
+        m = int(rng.integers(1, (nz - 1) // 2 + 1))
+        kind = int(kinds[int(rng.integers(0, len(kinds)))])
+        n = math.sqrt(eps)
+        if abs(beta) * n > LUMINAL_MARGIN or S > LUMINAL_MARGIN * n / (1.0 + n * abs(beta)):
+            continue
+        out.append(DispersionPoint(S, beta, eps, nz, m, 1.0, kind))
+    return out
+
+
+def dispersion_runs(points, steps: int, precision: int = F64) -> List[Problem]:
+    """Two ring runs per point, no source, no probes, starting from a
+    cosine in one field: D_k = cos(theta k), B = 0, and D = 0,
+    B_j = cos(theta (j + 1/2)) (B lives at j + 1/2).  After `steps` steps
+    the theta components of (D, B) of the two runs are the columns of the
+    steps-th power of the one-step amplification matrix."""
+    runs = []
+    for i, pt in enumerate(points):
+        k = np.arange(pt.nz, dtype=np.float64)
+        cd = np.cos(pt.theta * k)
+        cb = np.cos(pt.theta * (k + 0.5))
+        zero = np.zeros(pt.nz)
+        base = dict(nz=pt.nz, steps=steps, eps_rest=np.full(pt.nz, pt.eps),
+                    mu_rest=np.full(pt.nz, pt.mu), courant=pt.courant,
+                    beta=pt.beta, kind=pt.kind, precision=precision,
+                    src_cell=0, pulse=Pulse(amp=0.0), abc=ABC_PERIODIC)
+        runs.append(Problem(**base, init_d=cd, init_b=zero, label=f"disp{i}_d"))
+        runs.append(Problem(**base, init_d=zero, init_b=cb, label=f"disp{i}_b"))
+    return runs
