@@ -131,7 +131,7 @@ typedef struct gfdtd_problem {
     int32_t reserved0;
     int64_t nz;                  /* E nodes, >= 8                          */
     double courant;              /* S = dt/dz, > 0                         */
-    double beta;                 /* v/c, |beta| < 1                        */
+    double beta;                 /* v/c, |beta| < 1 and |beta| S <= 0.9    */
     const double *eps_rest;      /* host, nz, > 0 and finite               */
     const double *mu_rest;       /* host, nz, > 0 and finite               */
     int64_t src_cell;            /* 1..nz-2 (ring: 0..nz-1)                */

@@ -28,7 +28,7 @@ struct RunDesc {
     double S;              // Courant number
     double beta;
     double bS;             // beta * S (one rounding; also the shift rate)
-    double hb;             // beta / 2
+    double hb;             // S beta / 2 (the star fields are S-scaled)
     int32_t neg;           // beta < 0: Table 1 column b
     int32_t hl;            // halo lanes left of the owned lanes
     int32_t hr;            // halo lanes right of the owned lanes
@@ -37,9 +37,9 @@ struct RunDesc {
     int32_t pad0;
     void *D[2];            // ping-pong D (run precision)
     void *B[2];            // ping-pong B
-    const void *cE;        // E-node coefficient: 1/eps' or g mu'
-    const void *cH;        // H-node coefficient: 1/mu'  or g eps'
-    const void *gB;        // moving matter: g beta / 2 (else unused)
+    const void *cE;        // E-node coefficient: S/eps' or S g mu'
+    const void *cH;        // H-node coefficient: S/mu'  or S g eps'
+    const void *gB;        // moving matter: S g beta / 2 (else unused)
     const double *murL;    // left-end Mur coefficient per rest cell
     const double *murR;    // right-end Mur coefficient per rest cell
     const double *src;     // source samples, step n at [n-1]

@@ -12,14 +12,17 @@
 // ping-pong pair.  HBM traffic per cell-update is therefore about
 // 2 * 2 * sizeof(R) / T plus the halo overhead.
 //
-// Per step and cell (all in registers):
-//   E*   = cE D - hb (B_a + B_b)        (10c) with the Table 1 B average
-//   B'   = B - S (E*_{+1} - E*) - bS dB (10a) with the Table 1 dB/dz
-//   H*   = cH B' - hb (D_{+1} + D)      (10d) with the Table 1 D average
-//   D'   = D - S (H* - H*_{-1}) - bS dD (10b) with the Table 1 dD/dz
-// then the source, the end conditions and the probes.  cE, cH are 1/eps',
-// 1/mu' for a moving modulation; for moving matter cE = g mu', cH = g eps'
-// and hb is replaced by the per-cell g beta / 2.
+// Per step and cell (all in registers), with the star fields carried
+// scaled by the Courant number S (E~ = S E*, H~ = S H*):
+//   E~   = cE D - hb (B_a + B_b)          (10c) with the Table 1 B average
+//   B'   = B - (E~_{+1} - E~) - bS dB     (10a) with the Table 1 dB/dz
+//   H~   = cH B' - hb (D_{+1} + D)        (10d) with the Table 1 D average
+//   D'   = D - (H~ - H~_{-1}) - bS dD     (10b) with the Table 1 dD/dz
+// then the source, the end conditions and the probes.  cE, cH are S/eps',
+// S/mu' and hb = S beta / 2 for a moving modulation; for moving matter
+// cE = S g mu', cH = S g eps' and hb is the per-cell S g beta / 2.  Each
+// update is one difference and two fused multiply-adds (12 floating-point
+// instructions per cell and step).
 //
 // The moving profile: at time tau*S the rest profile has moved by
 // m = rint(beta S tau) whole cells (FP64 on every path), so each lane keeps
@@ -27,6 +30,8 @@
 // one shuffle, whenever m changes.
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "gfdtd.h"
 #include "gfdtd_internal.h"
@@ -37,15 +42,15 @@ namespace gfdtd {
 
 // Whole-wavefront shifts by one lane with DPP (wave_shr:1 / wave_shl:1):
 // one VALU move per 32-bit word, no LDS traffic.  The lane shifted in at
-// the wave edge reads 0.
+// the wave edge reads 0 (bound_ctrl), so no old value is needed.
 __device__ __forceinline__ int dpp_from_left(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ int dpp_from_right(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ float from_left(float v)     // lane i <- lane i-1
@@ -72,6 +77,16 @@ __device__ __forceinline__ double from_right(double v)
     const int lo = dpp_from_right((int)(u & 0xffffffffLL));
     const int hi = dpp_from_right((int)(u >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float fmad(float a, float b, float c)
+{
+    return __builtin_fmaf(a, b, c);
+}
+
+__device__ __forceinline__ double fmad(double a, double b, double c)
+{
+    return __builtin_fma(a, b, c);
 }
 
 template <typename R>
@@ -202,9 +217,16 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
 
     const double bS64 = rd->bS;
     const double beta64 = rd->beta;
-    const R S = (R)rd->S;
-    const R bS = (R)bS64;
-    const R hb = (R)rd->hb;
+    const double invS64 = 1.0 / rd->S;
+    // Star fields are carried scaled by S (E~ = S E*, H~ = S H*), with
+    // S-scaled coefficients, so that each of (10a) and (10b) is one
+    // difference and two fused multiply-adds:
+    //   B' = w0 B + w1 B_up + (E~ - E~_{+1}),  D' = w0 D + w1 D_up + (H~_{-1} - H~)
+    // with w0 = 1 - beta S, w1 = beta S, B_up = B_{-1} (column a, v >= 0)
+    // or w0 = 1 + beta S, w1 = -beta S, B_up = B_{+1} (column b, v < 0).
+    const R w0 = (R)(NEG ? 1.0 + bS64 : 1.0 - bS64);
+    const R w1 = (R)(NEG ? -bS64 : bS64);
+    const R hb = (R)rd->hb;             // S beta / 2
     const int hl = rd->hl;
     const int hr = rd->hr;
     const int abc = rd->abc;
@@ -239,11 +261,9 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     }
 
     // coefficients for the first step of the block: E nodes at n0-1/2,
-    // H nodes at n0.  Times are exact in FP64 and advanced by 1 per step.
-    double tauH = (double)n0;
-    double tauE = tauH - 0.5;          // = (n0 - 1) + 1/2 exactly
-    int mE = profile_shift32(bS64, tauE);
-    int mH = profile_shift32(bS64, tauH);
+    // H nodes at n0 (times exact in FP64).
+    const int mE = profile_shift32(bS64, (double)n0 - 0.5);
+    const int mH = profile_shift32(bS64, (double)n0);
     R ce[C], ch[C], ge[C], gh[C];
     if constexpr (RING) {
         int64_t iE = wrapi(kb - mE, nz);
@@ -328,7 +348,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     R Es[C], sums[C];
     R Bup = (R)0;     // B of the cell just outside this lane, upwind side
 
-    // E* of every cell from the current (D, B) and the E coefficients.
+    // E~ = S E* of every cell from the current (D, B) and the E
+    // coefficients ((10c) with the Table 1 B average, scaled by S).
     auto compute_es = [&]() __attribute__((always_inline)) {
         if constexpr (!NEG) {
             const R Bm1 = from_left(B[C - 1]);
@@ -352,9 +373,9 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             if constexpr (kMatter)
-                Es[c] = D[c] * ce[c] - ge[c] * sums[c];
+                Es[c] = fmad(D[c], ce[c], -(ge[c] * sums[c]));
             else
-                Es[c] = D[c] * ce[c] - hb * sums[c];
+                Es[c] = fmad(D[c], ce[c], -(hb * sums[c]));
         }
     };
 
@@ -364,7 +385,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         ownsProbe = ownsProbe || (kp >= own_lo && kp < own_hi);
     }
 
-    // Physical E = E* + beta Bbar at the owned probes, for time n-1/2.
+    // Physical E = E* + beta Bbar at the owned probes, for time n-1/2
+    // (E* = E~ / S).
     auto record = [&](int64_t n) __attribute__((always_inline)) {
         if (n < 2 || !ownsProbe)
             return;
@@ -378,73 +400,72 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const R sm = pick<R, C>(sums, cp);
             if (lane == lp)
                 rd->trace[(int64_t)q * steps + (n - 2)] =
-                    (double)e + beta64 * (0.5 * (double)sm);
+                    (double)e * invS64 + beta64 * (0.5 * (double)sm);
         }
     };
 
-    for (int s = 0; s < nsub; ++s) {
-        const int64_t n = n0 + s;
-        if (s > 0) {                      // H coefficients at time n
-            tauH += 1.0;
-            const int m = profile_shift32(bS64, tauH);
-            if (m != mH) {
-                shift_window<R, C, NEG>(ch);
-                if constexpr (kMatter)
-                    shift_window<R, C, NEG>(gh);
-                mH = m;
-            }
-        }
+    // Shifts of the coefficient windows.  Over one step the profile moves
+    // by 0 or dir = sign(beta) cells at each node type (|beta S| <= 0.9), so
+    // a shift moves a window by exactly one cell.
+    constexpr int dir = NEG ? -1 : 1;
+    auto shift_e = [&]() __attribute__((always_inline)) {
+        shift_window<R, C, NEG>(ce);
+        if constexpr (kMatter)
+            shift_window<R, C, NEG>(ge);
+    };
+    auto shift_h = [&]() __attribute__((always_inline)) {
+        shift_window<R, C, NEG>(ch);
+        if constexpr (kMatter)
+            shift_window<R, C, NEG>(gh);
+    };
 
+    // One time step n with fixed coefficient windows; mEn is the profile
+    // shift at the E time n+1/2 (read by the end conditions only).
+    auto one_step = [&](auto edge_tag, int64_t n, int mEn) __attribute__((always_inline)) {
+        constexpr bool kEdge = decltype(edge_tag)::value;
         compute_es();
-        record(n);
+        if constexpr (kEdge)
+            record(n);
 
-        // (10a) Faraday
+        // (10a) Faraday with the Table 1 dB/dz
         const R EsR = from_right(Es[0]);
         const R DR = from_right(D[0]);
         R Bn[C], Hs[C];
-        if constexpr (!NEG) {
-            const R Bm1 = Bup;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
-                const R bp = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bm1;
-                Bn[c] = B[c] - S * (esn - Es[c]) - bS * (B[c] - bp);
-            }
-        } else {
-            const R Bp1 = Bup;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
-                const R bn = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bp1;
-                Bn[c] = B[c] - S * (esn - Es[c]) - bS * (bn - B[c]);
-            }
+        for (int c = 0; c < C; ++c) {
+            const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
+            R bup;
+            if constexpr (!NEG)
+                bup = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bup;
+            else
+                bup = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bup;
+            Bn[c] = fmad(B[c], w0, fmad(w1, bup, Es[c] - esn));
         }
-        // (10d) H*
+        // (10d) H~ = S H* with the Table 1 D average
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const R dn = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
             if constexpr (kMatter)
-                Hs[c] = Bn[c] * ch[c] - gh[c] * (dn + D[c]);
+                Hs[c] = fmad(Bn[c], ch[c], -(gh[c] * (dn + D[c])));
             else
-                Hs[c] = Bn[c] * ch[c] - hb * (dn + D[c]);
+                Hs[c] = fmad(Bn[c], ch[c], -(hb * (dn + D[c])));
         }
-        // (10b) Ampere
+        // (10b) Ampere with the Table 1 dD/dz
         const R HsL = from_left(Hs[C - 1]);
         const R DL = from_left(D[C - 1]);
         R Dn[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const R hp = (c >= 1) ? Hs[c >= 1 ? c - 1 : 0] : HsL;
-            if constexpr (!NEG) {
-                const R dp = (c >= 1) ? D[c >= 1 ? c - 1 : 0] : DL;
-                Dn[c] = D[c] - S * (Hs[c] - hp) - bS * (D[c] - dp);
-            } else {
-                const R dn = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
-                Dn[c] = D[c] - S * (Hs[c] - hp) - bS * (dn - D[c]);
-            }
+            R dup;
+            if constexpr (!NEG)
+                dup = (c >= 1) ? D[c >= 1 ? c - 1 : 0] : DL;
+            else
+                dup = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
+            Dn[c] = fmad(D[c], w0, fmad(w1, dup, hp - Hs[c]));
         }
         // soft source
-        if (hasSrc && n <= rd->nsrc) {
+        if (kEdge && hasSrc && n <= rd->nsrc) {
             const R g = (R)rd->src[n - 1];
             if constexpr (RING) {
                 if (smask) {
@@ -461,9 +482,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         }
         // end nodes, at time n+1/2
-        tauE += 1.0;
-        const int mEn = profile_shift32(bS64, tauE);
-        if (touchL) {
+        if (kEdge && touchL) {
             const int l0 = (int)(-x0 / C);
             if (lane == l0) {
                 if (abc == GFDTD_ABC_MUR1) {
@@ -474,7 +493,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 }
             }
         }
-        if (touchR) {
+        if (kEdge && touchR) {
             const int64_t r = nz - 1 - x0;
             const int lr = (int)(r / C);
             const int cr = (int)(r % C);
@@ -497,22 +516,61 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             D[c] = Dn[c];
             B[c] = Bn[c];
         }
-        if (touchL || touchR)
+        if (kEdge && (touchL || touchR))
             ghosts(B);
+    };
 
-        // E coefficients at time n+1/2 for the next step
-        if (mEn != mE) {
-            shift_window<R, C, NEG>(ce);
-            if constexpr (kMatter)
-                shift_window<R, C, NEG>(ge);
-            mE = mEn;
+    // The step loop.  The shift schedule of 64 steps at a time is computed
+    // in FP64 by the per-node rule m = rint(beta S tau), one step per lane,
+    // and kept as wave-wide bit masks: bit j of hmask = the H window moves
+    // before step j of the chunk, bit j of emask = the E window moves after
+    // it.  The steps between two moves run with fixed windows.  The loop is
+    // compiled twice: tiles holding an end, the source or a probe run the
+    // full step; interior tiles (nearly all of them) run one without that
+    // code.
+    auto steps_loop = [&](auto edge_tag) __attribute__((always_inline)) {
+        constexpr bool kEdge = decltype(edge_tag)::value;
+        int mEc = mE;                       // E shift at the current n - 1/2
+        for (int s0 = 0; s0 < nsub; s0 += kWave) {
+            const int len = nsub - s0 < kWave ? nsub - s0 : kWave;
+            const int sl = s0 + lane;
+            const double tn = (double)(n0 + sl);
+            const bool hbit = sl > 0 && sl < nsub &&
+                              profile_shift32(bS64, tn) != profile_shift32(bS64, tn - 1.0);
+            const bool ebit = sl < nsub &&
+                              profile_shift32(bS64, tn + 0.5) != profile_shift32(bS64, tn - 0.5);
+            const uint64_t hmask = __ballot(hbit);
+            const uint64_t emask = __ballot(ebit);
+            const uint64_t bmask = emask | (hmask >> 1);  // a move after step j
+            if (hmask & 1ull)
+                shift_h();
+            int j = 0;
+            while (j < len) {
+                const uint64_t rest = bmask >> j;
+                const int stop = rest ? j + (int)__builtin_ctzll(rest) : len - 1;
+                for (int q = j; q <= stop; ++q) {
+                    const int mEn = mEc + (((emask >> q) & 1ull) ? dir : 0);
+                    one_step(edge_tag, n0 + s0 + q, mEn);
+                }
+                if ((emask >> stop) & 1ull) {
+                    shift_e();
+                    mEc += dir;
+                }
+                if (stop + 1 < len && ((hmask >> (stop + 1)) & 1ull))
+                    shift_h();
+                j = stop + 1;
+            }
         }
-    }
 
-    if (last) {               // the run ends in this block: E at N+1/2
-        compute_es();
-        record(steps + 1);
-    }
+        if (kEdge && last && ownsProbe) {   // the run ends in this block: E at N+1/2
+            compute_es();
+            record(steps + 1);
+        }
+    };
+    if (touchL || touchR || hasSrc || ownsProbe)
+        steps_loop(std::true_type{});
+    else
+        steps_loop(std::false_type{});
 
     if (lane >= hl && lane < kWave - hr) {
         store_cells<R, C>(Ddst + kb, D);
@@ -606,14 +664,15 @@ __device__ __forceinline__ void prep_cell(const PrepDesc &d, int64_t i)
     const double eps = d.eps[i];
     const double mu = d.mu[i];
     const double b = d.beta;
+    // coefficients of the S-scaled star fields (E~ = S E*, H~ = S H*)
     if (d.kind == GFDTD_MATTER) {
-        const double g = (1.0 - b * b) / (eps * mu - b * b);
-        static_cast<R *>(d.cE)[i] = (R)(g * mu);
-        static_cast<R *>(d.cH)[i] = (R)(g * eps);
-        static_cast<R *>(d.gB)[i] = (R)(g * b * 0.5);
+        const double gS = (1.0 - b * b) / (eps * mu - b * b) * d.S;
+        static_cast<R *>(d.cE)[i] = (R)(gS * mu);
+        static_cast<R *>(d.cH)[i] = (R)(gS * eps);
+        static_cast<R *>(d.gB)[i] = (R)(gS * b * 0.5);
     } else {
-        static_cast<R *>(d.cE)[i] = (R)(1.0 / eps);
-        static_cast<R *>(d.cH)[i] = (R)(1.0 / mu);
+        static_cast<R *>(d.cE)[i] = (R)(d.S / eps);
+        static_cast<R *>(d.cH)[i] = (R)(d.S / mu);
     }
     // Mur coefficients (S u - 1)/(S u + 1) for the medium an end node sees
     // when rest cell i sits under it: the left end pairs E cell i with H

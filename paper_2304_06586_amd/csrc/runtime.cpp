@@ -74,8 +74,10 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
         return fail(GFDTD_E_INVALID, "Courant number must be finite and > 0");
     if (!std::isfinite(p->beta) || std::fabs(p->beta) >= 1.0)
         return fail(GFDTD_E_INVALID, "|beta| must be < 1");
-    if (std::fabs(p->beta * p->courant) >= 1.0)
-        return fail(GFDTD_E_INVALID, "|beta| S must be < 1");
+    // the profile then moves at most one cell per step at each node type
+    // (every stable problem has |beta| S <= 1/2)
+    if (std::fabs(p->beta * p->courant) > 0.9)
+        return fail(GFDTD_E_INVALID, "|beta| S must be <= 0.9");
     if (!p->eps_rest || !p->mu_rest)
         return fail(GFDTD_E_INVALID, "eps_rest / mu_rest missing");
     for (int64_t i = 0; i < p->nz; ++i)
@@ -706,7 +708,7 @@ void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
     rd.S = p.courant;
     rd.beta = p.beta;
     rd.bS = p.beta * p.courant;
-    rd.hb = 0.5 * p.beta;
+    rd.hb = 0.5 * p.beta * p.courant;
     rd.neg = p.beta < 0.0;
     rd.hl = hl;
     rd.hr = hr;
