@@ -20,9 +20,11 @@
 //   D'   = D - (H~ - H~_{-1}) - bS dD     (10b) with the Table 1 dD/dz
 // then the source, the end conditions and the probes.  cE, cH are S/eps',
 // S/mu' and hb = S beta / 2 for a moving modulation; for moving matter
-// cE = S g mu', cH = S g eps' and hb is the per-cell S g beta / 2.  Each
-// update is one difference and two fused multiply-adds (12 floating-point
-// instructions per cell and step).
+// cE = S g mu', cH = S g eps' and hb is the per-cell S g beta / 2.  The
+// curl and velocity terms of (10a)/(10b) are telescoped into one
+// difference of per-cell sums (P = E~ + bS B_up, X = H~ + bS D_sel), which
+// keeps a uniform field exactly uniform and needs 12 floating-point
+// instructions per cell and step.
 //
 // The moving profile: at time tau*S the rest profile has moved by
 // m = rint(beta S tau) whole cells (FP64 on every path), so each lane keeps
@@ -219,13 +221,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     const double beta64 = rd->beta;
     const double invS64 = 1.0 / rd->S;
     // Star fields are carried scaled by S (E~ = S E*, H~ = S H*), with
-    // S-scaled coefficients, so that each of (10a) and (10b) is one
-    // difference and two fused multiply-adds:
-    //   B' = w0 B + w1 B_up + (E~ - E~_{+1}),  D' = w0 D + w1 D_up + (H~_{-1} - H~)
-    // with w0 = 1 - beta S, w1 = beta S, B_up = B_{-1} (column a, v >= 0)
-    // or w0 = 1 + beta S, w1 = -beta S, B_up = B_{+1} (column b, v < 0).
-    const R w0 = (R)(NEG ? 1.0 + bS64 : 1.0 - bS64);
-    const R w1 = (R)(NEG ? -bS64 : bS64);
+    // S-scaled coefficients.
+    const R bS = (R)bS64;
     const R hb = (R)rd->hb;             // S beta / 2
     const int hl = rd->hl;
     const int hr = rd->hr;
@@ -346,36 +343,37 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     const int64_t own_hi = x0 + W - (int64_t)hr * C;
 
     R Es[C], sums[C];
+    R D2[C], B2[C];   // second register set of the ping-pong step pair
     R Bup = (R)0;     // B of the cell just outside this lane, upwind side
 
     // E~ = S E* of every cell from the current (D, B) and the E
     // coefficients ((10c) with the Table 1 B average, scaled by S).
-    auto compute_es = [&]() __attribute__((always_inline)) {
+    auto compute_es = [&](const R (&Dc)[C], const R (&Bc)[C]) __attribute__((always_inline)) {
         if constexpr (!NEG) {
-            const R Bm1 = from_left(B[C - 1]);
-            const R Bm2 = from_left(B[C - 2]);
+            const R Bm1 = from_left(Bc[C - 1]);
+            const R Bm2 = from_left(Bc[C - 2]);
             Bup = Bm1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const R b1 = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bm1;
-                const R b2 = (c >= 2) ? B[c >= 2 ? c - 2 : 0] : (c == 1 ? Bm1 : Bm2);
+                const R b1 = (c >= 1) ? Bc[c >= 1 ? c - 1 : 0] : Bm1;
+                const R b2 = (c >= 2) ? Bc[c >= 2 ? c - 2 : 0] : (c == 1 ? Bm1 : Bm2);
                 sums[c] = b1 + b2;
             }
         } else {
-            const R Bp1 = from_right(B[0]);
+            const R Bp1 = from_right(Bc[0]);
             Bup = Bp1;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const R b1 = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bp1;
-                sums[c] = b1 + B[c];
+                const R b1 = (c + 1 < C) ? Bc[c + 1 < C ? c + 1 : 0] : Bp1;
+                sums[c] = b1 + Bc[c];
             }
         }
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             if constexpr (kMatter)
-                Es[c] = fmad(D[c], ce[c], -(ge[c] * sums[c]));
+                Es[c] = fmad(Dc[c], ce[c], -(ge[c] * sums[c]));
             else
-                Es[c] = fmad(D[c], ce[c], -(hb * sums[c]));
+                Es[c] = fmad(Dc[c], ce[c], -(hb * sums[c]));
         }
     };
 
@@ -419,50 +417,65 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             shift_window<R, C, NEG>(gh);
     };
 
-    // One time step n with fixed coefficient windows; mEn is the profile
-    // shift at the E time n+1/2 (read by the end conditions only).
-    auto one_step = [&](auto edge_tag, int64_t n, int mEn) __attribute__((always_inline)) {
+    // One time step n with fixed coefficient windows, from (Di, Bi) to
+    // (Dn, Bn); mEn is the profile shift at the E time n+1/2 (read by the
+    // end conditions only).
+    auto one_step = [&](auto edge_tag, int64_t n, int mEn, const R (&Di)[C],
+                        const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
+                        __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
-        compute_es();
+        compute_es(Di, Bi);
         if constexpr (kEdge)
             record(n);
 
-        // (10a) Faraday with the Table 1 dB/dz
-        const R EsR = from_right(Es[0]);
-        const R DR = from_right(D[0]);
-        R Bn[C], Hs[C];
+        // (10a) Faraday with the Table 1 dB/dz, in telescoped form:
+        //   P_k = E~_k + bS B_up(k),  B' = B + (P_k - P_{k+1}),
+        // B_up(k) = B_{k-1} (column a) or B_k (column b).  A uniform field
+        // stays exactly uniform.
+        R P[C], Hs[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const R esn = (c + 1 < C) ? Es[c + 1 < C ? c + 1 : 0] : EsR;
-            R bup;
+            R bsel;
             if constexpr (!NEG)
-                bup = (c >= 1) ? B[c >= 1 ? c - 1 : 0] : Bup;
+                bsel = (c >= 1) ? Bi[c >= 1 ? c - 1 : 0] : Bup;
             else
-                bup = (c + 1 < C) ? B[c + 1 < C ? c + 1 : 0] : Bup;
-            Bn[c] = fmad(B[c], w0, fmad(w1, bup, Es[c] - esn));
+                bsel = Bi[c];
+            P[c] = fmad(bS, bsel, Es[c]);
+        }
+        const R PR = from_right(P[0]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const R pn = (c + 1 < C) ? P[c + 1 < C ? c + 1 : 0] : PR;
+            Bn[c] = Bi[c] + (P[c] - pn);
         }
         // (10d) H~ = S H* with the Table 1 D average
+        const R DR = from_right(Di[0]);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const R dn = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
+            const R dn = (c + 1 < C) ? Di[c + 1 < C ? c + 1 : 0] : DR;
             if constexpr (kMatter)
-                Hs[c] = fmad(Bn[c], ch[c], -(gh[c] * (dn + D[c])));
+                Hs[c] = fmad(Bn[c], ch[c], -(gh[c] * (dn + Di[c])));
             else
-                Hs[c] = fmad(Bn[c], ch[c], -(hb * (dn + D[c])));
+                Hs[c] = fmad(Bn[c], ch[c], -(hb * (dn + Di[c])));
         }
-        // (10b) Ampere with the Table 1 dD/dz
-        const R HsL = from_left(Hs[C - 1]);
-        const R DL = from_left(D[C - 1]);
-        R Dn[C];
+        // (10b) Ampere with the Table 1 dD/dz, telescoped:
+        //   X_k = H~_k + bS D_sel(k),  D' = D + (X_{k-1} - X_k),
+        // D_sel(k) = D_k (column a) or D_{k+1} (column b).
+        R X[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const R hp = (c >= 1) ? Hs[c >= 1 ? c - 1 : 0] : HsL;
-            R dup;
+            R dsel;
             if constexpr (!NEG)
-                dup = (c >= 1) ? D[c >= 1 ? c - 1 : 0] : DL;
+                dsel = Di[c];
             else
-                dup = (c + 1 < C) ? D[c + 1 < C ? c + 1 : 0] : DR;
-            Dn[c] = fmad(D[c], w0, fmad(w1, dup, hp - Hs[c]));
+                dsel = (c + 1 < C) ? Di[c + 1 < C ? c + 1 : 0] : DR;
+            X[c] = fmad(bS, dsel, Hs[c]);
+        }
+        const R XL = from_left(X[C - 1]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const R xp = (c >= 1) ? X[c >= 1 ? c - 1 : 0] : XL;
+            Dn[c] = Di[c] + (xp - X[c]);
         }
         // soft source
         if (kEdge && hasSrc && n <= rd->nsrc) {
@@ -487,7 +500,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             if (lane == l0) {
                 if (abc == GFDTD_ABC_MUR1) {
                     const R cL = (R)rd->murL[clampi(-mEn, 0, nz - 1)];
-                    Dn[0] = D[1] + cL * (Dn[1] - D[0]);
+                    Dn[0] = Di[1] + cL * (Dn[1] - Di[0]);
                 } else {
                     Dn[0] = (R)0;
                 }
@@ -497,27 +510,22 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int64_t r = nz - 1 - x0;
             const int lr = (int)(r / C);
             const int cr = (int)(r % C);
-            const R dlo = from_left(D[C - 1]);
+            const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
             const R cR = (R)rd->murR[clampi(nz - 1 - mEn, 0, nz - 1)];
             if (lane == lr) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     if (c == cr) {
-                        const R po = (c >= 1) ? D[c >= 1 ? c - 1 : 0] : dlo;
+                        const R po = (c >= 1) ? Di[c >= 1 ? c - 1 : 0] : dlo;
                         const R pn = (c >= 1) ? Dn[c >= 1 ? c - 1 : 0] : dln;
-                        Dn[c] = (abc == GFDTD_ABC_MUR1) ? po + cR * (pn - D[c]) : (R)0;
+                        Dn[c] = (abc == GFDTD_ABC_MUR1) ? po + cR * (pn - Di[c]) : (R)0;
                     }
                 }
             }
         }
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            D[c] = Dn[c];
-            B[c] = Bn[c];
-        }
         if (kEdge && (touchL || touchR))
-            ghosts(B);
+            ghosts(Bn);
     };
 
     // The step loop.  The shift schedule of 64 steps at a time is computed
@@ -548,9 +556,23 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             while (j < len) {
                 const uint64_t rest = bmask >> j;
                 const int stop = rest ? j + (int)__builtin_ctzll(rest) : len - 1;
-                for (int q = j; q <= stop; ++q) {
-                    const int mEn = mEc + (((emask >> q) & 1ull) ? dir : 0);
-                    one_step(edge_tag, n0 + s0 + q, mEn);
+                // two steps at a time, ping-ponging between register sets
+                // (D, B) and (D2, B2), so no copies between steps
+                auto mEn_of = [&](int q) __attribute__((always_inline)) {
+                    return mEc + (((emask >> q) & 1ull) ? dir : 0);
+                };
+                int q = j;
+                for (; q + 1 <= stop; q += 2) {
+                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q + 1, mEn_of(q + 1), D2, B2, D, B);
+                }
+                if (q <= stop) {
+                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), D, B, D2, B2);
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        D[c] = D2[c];
+                        B[c] = B2[c];
+                    }
                 }
                 if ((emask >> stop) & 1ull) {
                     shift_e();
@@ -563,7 +585,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
 
         if (kEdge && last && ownsProbe) {   // the run ends in this block: E at N+1/2
-            compute_es();
+            compute_es(D, B);
             record(steps + 1);
         }
     };

@@ -150,6 +150,10 @@ def load_library(path: str = LIB_PATH):
     global _lib
     with _lock:
         if _lib is None:
+            # torch first: its HIP runtime (soname libamdhip64.so.7) then
+            # satisfies the library's dependency, so the process holds one
+            # runtime, the one that owns the torch-allocated device memory
+            import torch  # noqa: F401
             if not os.path.exists(path):
                 raise RuntimeError(
                     f"{path} is missing: build the HIP library first "
