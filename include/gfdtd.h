@@ -193,7 +193,7 @@ gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
 #define GFDTD_VARIANT_TILED 2    /* register tiles, several steps a launch */
 
 /*
- * Execution options (NULL = automatic).  cells_per_lane in {4, 8, 16}
+ * Execution options (NULL = automatic).  cells_per_lane in {4, 8, 12, 16}
  * (0 = auto), block_steps = temporal block depth, steps per launch
  * (0 = auto; 1 for GFDTD_VARIANT_STEP), use_graph: -1 auto, 0 plain
  * launches, 1 capture the launch sequence in a hipGraph.

@@ -635,6 +635,10 @@ static hipError_t launch_tiles_c(int C, const RunDesc *runs,
         hipLaunchKernelGGL((k_tiles<R, 8, KIND, RING>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
+    case 12:
+        hipLaunchKernelGGL((k_tiles<R, 12, KIND, RING>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles);
+        break;
     case 16:
         hipLaunchKernelGGL((k_tiles<R, 16, KIND, RING>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);

@@ -334,22 +334,24 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 
 // --------------------------------------------------------------- tiling
 
-// Tiling defaults from measurements on MI355X: 8 cells per lane and 24
-// steps per launch for batches that fill the GPU; 4 cells per lane when the
-// group holds few cells (more, narrower tiles keep more SIMDs busy).
+// Tiling defaults from measurements on MI355X (full-occupancy launches of
+// the 4096-run crystal batch): FP32 12 cells per lane and 32 steps per
+// launch, FP64 8 and 32 (FP64 holds twice the registers per cell); 4 cells
+// per lane and 24 steps when the group holds few cells (more, narrower
+// tiles keep more SIMDs busy).
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
                    int64_t total_cells, int &C, int &T)
 {
-    (void)precision;
     const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
+    const bool small = total_cells < (int64_t)4 << 20;
     C = (ex && ex->cells_per_lane) ? ex->cells_per_lane
-                                   : (total_cells < (int64_t)4 << 20 ? 4 : 8);
+                                   : (small ? 4 : (precision == GFDTD_F32 ? 12 : 8));
     if (variant == GFDTD_VARIANT_STEP)
         T = 1;
     else if (ex && ex->block_steps > 0)
         T = ex->block_steps;
     else
-        T = 24;
+        T = small ? 24 : 32;
     if (max_steps > 0 && T > max_steps)
         T = (int)std::max<int64_t>(1, max_steps);
 }
@@ -381,8 +383,8 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
     if (ex && ex->struct_size < sizeof(gfdtd_exec))
         return fail(GFDTD_E_INVALID, "exec struct_size too small");
     if (ex && ex->cells_per_lane && ex->cells_per_lane != 4 &&
-        ex->cells_per_lane != 8 && ex->cells_per_lane != 16)
-        return fail(GFDTD_E_INVALID, "cells_per_lane must be 4, 8 or 16");
+        ex->cells_per_lane != 8 && ex->cells_per_lane != 12 && ex->cells_per_lane != 16)
+        return fail(GFDTD_E_INVALID, "cells_per_lane must be 4, 8, 12 or 16");
     if (ex && (ex->block_steps < 0 || ex->block_steps > 256))
         return fail(GFDTD_E_INVALID, "block_steps outside 0..256");
     runs.resize(count);
@@ -593,7 +595,7 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
         const int defC = G.C, defT = G.T;
         int bestC = G.C, bestT = G.T;
         double best = 1e300, def_time = 1e300;
-        const int Cs[] = {4, 8, 16};
+        const int Cs[] = {4, 8, 12, 16};
         const int Ts[] = {8, 16, 24, 32, 48, 64};
         for (int C : Cs)
             for (int T : Ts) {

@@ -244,11 +244,11 @@ struct Server {
         pool_base = static_cast<char *>(cfg->pool);
         pool_bytes = cfg->pool_bytes;
         max_slots = cfg->max_slots;
-        gfdtd_exec ex{};
-        ex.struct_size = sizeof ex;
-        ex.block_steps = cfg->block_steps;
-        choose_tiling(GFDTD_F32, &ex, 0, INT64_MAX, Cg[0], T);
-        choose_tiling(GFDTD_F64, &ex, 0, INT64_MAX, Cg[1], T);
+        // Served requests are small and short next to a batch: 8 cells per
+        // lane and 24 steps per block (measured on the serving mix; wider
+        // tiles and deeper blocks lowered throughput and raised latency).
+        Cg[0] = Cg[1] = 8;
+        T = cfg->block_steps > 0 ? cfg->block_steps : 24;
         // two copies of the run and tile tables at the front of the pool;
         // a tile stores at least 64 cells and a run costs more than 32
         // bytes per cell, which bounds the tiles the pool can hold
