@@ -41,6 +41,14 @@
  * eps(r - v t)), rounded to whole cells: at time t = tau S the profile has
  * moved by m = rint(beta S tau) cells and node x reads rest cell x - m
  * (clamped to the grid, wrapped on a ring).
+ *
+ * Finite-duration modulation (the space-time slabs with temporal corners
+ * that the footnote to the transfer-matrix method of App. B.3 sets apart):
+ * when `windowed` is set, the moving profile exists only for node times t
+ * with t_on <= t < t_off; at other times every node sees the uniform
+ * background (eps_bg, mu_bg).  D and B carry over unchanged across the
+ * switch (the temporal-interface conditions the FDTD update enforces by
+ * itself, as noted in the footnote to Section 2).  Moving modulation only.
  */
 #include <math.h>
 #include <stdint.h>
@@ -70,6 +78,9 @@ typedef struct {
     const double *init_d;      /* optional D^{1/2}, nz                    */
     const double *init_b;      /* optional B^{0}, nz (last slot unused
                                   unless the ends are periodic)           */
+    int32_t windowed;          /* 1: modulation only for t_on <= t < t_off */
+    double t_on, t_off;
+    double eps_bg, mu_bg;      /* the medium outside that time window     */
 } oracle_problem;
 
 typedef struct {
@@ -100,6 +111,26 @@ static double at(const double *a, int64_t i, int64_t n, int ring)
     if (ring)
         return a[wrapi(i, n)];
     return a[clampi(i, 0, n - 1)];
+}
+
+/* Whether the moving profile exists at node time tau*S. */
+static int modulated(const oracle_problem *p, double tau)
+{
+    if (!p->windowed)
+        return 1;
+    const double t = tau * p->S;
+    return t >= p->t_on && t < p->t_off;
+}
+
+/* Rest permittivity / permeability of rest cell i at node time tau*S. */
+static double eps_of(const oracle_problem *p, int64_t i, double tau)
+{
+    return modulated(p, tau) ? p->eps_rest[i] : p->eps_bg;
+}
+
+static double mu_of(const oracle_problem *p, int64_t i, double tau)
+{
+    return modulated(p, tau) ? p->mu_rest[i] : p->mu_bg;
 }
 
 /* Whole-cell displacement of the moving profile at time tau*S. */
@@ -147,6 +178,9 @@ int oracle_solve(const oracle_problem *p, int64_t steps, oracle_result *r)
     const int64_t nz = p->nz;
     if (nz < 4 || steps < 0 || !(p->S > 0.0))
         return 1;
+    if (p->windowed && (p->kind != OR_MODULATION || !(p->eps_bg > 0.0) ||
+                        !(p->mu_bg > 0.0)))
+        return 1;
     const int ring = (p->abc == OR_PERIODIC);
     const int64_t nh = ring ? nz : nz - 1;          /* H nodes            */
     const double S = p->S;
@@ -189,7 +223,7 @@ int oracle_solve(const oracle_problem *p, int64_t steps, oracle_result *r)
                 const double g = (1.0 - b2) / (e * m - b2);
                 Es[k] = g * (m * D[k] - beta * Bbar);
             } else {
-                Es[k] = D[k] / p->eps_rest[i] - beta * Bbar;
+                Es[k] = D[k] / eps_of(p, i, 0.5) - beta * Bbar;
             }
         }
     }
@@ -213,7 +247,7 @@ int oracle_solve(const oracle_problem *p, int64_t steps, oracle_result *r)
                 const double g = (1.0 - b2) / (e * m - b2);
                 Hs[j] = g * (e * B[j] - beta * Dbar);
             } else {
-                Hs[j] = B[j] / p->mu_rest[i] - beta * Dbar;
+                Hs[j] = B[j] / mu_of(p, i, (double)n) - beta * Dbar;
             }
         }
 
@@ -240,8 +274,9 @@ int oracle_solve(const oracle_problem *p, int64_t steps, oracle_result *r)
             const int64_t hL = clampi(0 - mE, 0, nz - 2);
             const int64_t eR = clampi(nz - 1 - mE, 0, nz - 1);
             const int64_t hR = clampi(nz - 2 - mE, 0, nz - 2);
-            const double nL = sqrt(p->eps_rest[eL] * p->mu_rest[hL]);
-            const double nR = sqrt(p->eps_rest[eR] * p->mu_rest[hR]);
+            const double te = (double)n + 0.5;
+            const double nL = sqrt(eps_of(p, eL, te) * mu_of(p, hL, te));
+            const double nR = sqrt(eps_of(p, eR, te) * mu_of(p, hR, te));
             const double cL = mur_coefficient(S, exit_speed(p->kind, nL, beta, -1));
             const double cR = mur_coefficient(S, exit_speed(p->kind, nR, beta, +1));
             Dn[0] = D[1] + cL * (Dn[1] - D[0]);
@@ -261,7 +296,7 @@ int oracle_solve(const oracle_problem *p, int64_t steps, oracle_result *r)
                 const double g = (1.0 - b2) / (e * m - b2);
                 Es[k] = g * (m * D[k] - beta * Bbar);
             } else {
-                Es[k] = D[k] / p->eps_rest[i] - beta * Bbar;
+                Es[k] = D[k] / eps_of(p, i, (double)n + 0.5) - beta * Bbar;
             }
         }
 

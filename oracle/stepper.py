@@ -30,6 +30,8 @@ class _Problem(C.Structure):
         ("nprobe", C.c_int32), ("probe_cells", _P_I64),
         ("nfreq", C.c_int32), ("omegas", _P_D),
         ("init_d", _P_D), ("init_b", _P_D),
+        ("windowed", C.c_int32), ("t_on", C.c_double), ("t_off", C.c_double),
+        ("eps_bg", C.c_double), ("mu_bg", C.c_double),
     ]
 
 
@@ -98,6 +100,11 @@ def solve(problem, steps: Optional[int] = None,
                   float(p.pulse.tau), float(p.pulse.phase), float(p.pulse.t_off),
                   len(probes), _ptr(probes, _P_I64), len(omegas), _ptr(omegas),
                   _ptr(init_d), _ptr(init_b))
+    win = getattr(p, "window", None)
+    if win is not None:
+        pr.windowed = 1
+        pr.t_on, pr.t_off = float(win.t_on), float(win.t_off)
+        pr.eps_bg, pr.mu_bg = float(win.eps_bg), float(win.mu_bg)
     nprobe, nfreq = len(probes), len(omegas)
     trace = np.zeros((nprobe, steps))
     dre = np.zeros((nprobe, nfreq))

@@ -315,8 +315,15 @@ def _step_matrix(p, n):
     mE_prev = int(np.rint(bS * (n - 0.5)))
     mH = int(np.rint(bS * n))
     mE = int(np.rint(bS * (n + 0.5)))
-    eps_at = lambda k, m: p.eps_rest[min(max(k - m, 0), nz - 1)]
-    mu_at = lambda j, m: p.mu_rest[min(max(j - m, 0), nz - 2)]
+    win = getattr(p, "window", None)
+
+    def on(tau):             # the moving profile exists at time tau S
+        return win is None or win.t_on <= tau * S < win.t_off
+
+    eps_at = lambda k, m, tau: (p.eps_rest[min(max(k - m, 0), nz - 1)]
+                                if on(tau) else win.eps_bg)
+    mu_at = lambda j, m, tau: (p.mu_rest[min(max(j - m, 0), nz - 2)]
+                               if on(tau) else win.mu_bg)
     N = nz + nh
     iD = lambda k: k
     iB = lambda j: nz + j
@@ -330,7 +337,7 @@ def _step_matrix(p, n):
 
     Es = np.zeros((nz, N))
     for k in range(nz):
-        Es[k, iD(k)] = 1.0 / eps_at(k, mE_prev)
+        Es[k, iD(k)] = 1.0 / eps_at(k, mE_prev, n - 0.5)
         Es[k] -= beta * bbar_row(k)
     Bn = np.zeros((nh, N))
     for j in range(nh):
@@ -344,7 +351,7 @@ def _step_matrix(p, n):
             Bn[j, iB(min(j + 1, nh - 1))] -= bS
     Hs = np.zeros((nh, N))
     for j in range(nh):
-        Hs[j] = Bn[j] / mu_at(j, mH)
+        Hs[j] = Bn[j] / mu_at(j, mH, n)
         Hs[j, iD(j)] -= 0.5 * beta
         Hs[j, iD(j + 1)] -= 0.5 * beta
     Dn = np.zeros((nz, N))
@@ -364,8 +371,8 @@ def _step_matrix(p, n):
         s[iD(p.src_cell)] = p.pulse.amp * math.sin(
             p.pulse.omega * (t - p.pulse.t0) + p.pulse.phase) * math.exp(-u * u)
     # first-order Mur rows (velocity ignored for a moving modulation)
-    nL = math.sqrt(eps_at(0, mE) * mu_at(0, mE))
-    nR = math.sqrt(eps_at(nz - 1, mE) * mu_at(nz - 2, mE))
+    nL = math.sqrt(eps_at(0, mE, n + 0.5) * mu_at(0, mE, n + 0.5))
+    nR = math.sqrt(eps_at(nz - 1, mE, n + 0.5) * mu_at(nz - 2, mE, n + 0.5))
     cL = (S / nL - 1) / (S / nL + 1)
     cR = (S / nR - 1) / (S / nR + 1)
     sL = s[iD(1)]
@@ -382,14 +389,19 @@ def _step_matrix(p, n):
     return M, s
 
 
-@pytest.mark.parametrize("beta,nz", [(0.35, 12), (-0.4, 16), (0.0, 9)])
-def test_brute_force_matrix(beta, nz):
+@pytest.mark.parametrize("beta,nz,window", [
+    (0.35, 12, None), (-0.4, 16, None), (0.0, 9, None),
+    (0.35, 12, W.TimeWindow(3.1, 14.9, 2.5, 1.3)),
+    (-0.4, 16, W.TimeWindow(-1.0, 7.25, 1.7, 1.0)),
+    (0.3, 11, W.TimeWindow(12.0, 1e9, 3.0, 1.2))])
+def test_brute_force_matrix(beta, nz, window):
     """The whole stepper (interior stencil, ghosts, source, Mur ends,
-    moving profile) against explicit per-step matrices on tiny grids."""
+    moving profile, a modulation switched on and/or off in time) against
+    explicit per-step matrices on tiny grids."""
     p = W.small_case(nz, 50, beta, seed=11, structure="random")
     p = p.replace(src_cell=nz // 2, pulse=W.Pulse(amp=1.0, omega=0.9, t0=4.0,
                                                    tau=3.0, phase=0.3,
-                                                   t_off=20.0))
+                                                   t_off=20.0), window=window)
     rng = np.random.default_rng(7)
     d0 = rng.normal(size=nz)
     b0 = np.zeros(nz)

@@ -71,6 +71,18 @@ def default_omegas(omega0: float, nfreq: int = 64,
     return omega0 * np.linspace(lo, hi, nfreq)
 
 
+@dataclasses.dataclass(frozen=True)
+class TimeWindow:
+    """A moving modulation that exists only for t_on <= t < t_off: before
+    and after, the whole grid is the uniform background (eps_bg, mu_bg).
+    The switches are temporal interfaces, the corners of the space-time
+    slab are where they meet the moving boundaries."""
+    t_on: float
+    t_off: float
+    eps_bg: float = 1.0
+    mu_bg: float = 1.0
+
+
 @dataclasses.dataclass
 class Problem:
     """One scattering solve: the quantities the paper's statement of the
@@ -103,6 +115,8 @@ class Problem:
     # with ends the last B entry is unused); None means zero
     init_d: Optional[np.ndarray] = None
     init_b: Optional[np.ndarray] = None
+    # finite-duration modulation (moving modulation only), or None: always
+    window: Optional[TimeWindow] = None
 
     def __post_init__(self):
         self.eps_rest = np.ascontiguousarray(self.eps_rest, dtype=np.float64)
