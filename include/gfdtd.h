@@ -92,6 +92,8 @@ const char *gfdtd_last_error(void);
 #define GFDTD_FLAG_ALLOW_UNSTABLE 2u /* skip the pre-flight rejection      */
 #define GFDTD_FLAG_KEEP_FIELDS 4u    /* server: keep the final fields until
                                         the request is polled              */
+#define GFDTD_FLAG_TIME_WINDOW 8u    /* finite-duration modulation: see
+                                        t_on, t_off, eps_bg, mu_bg         */
 
 #define GFDTD_MAX_PROBES 64
 
@@ -111,6 +113,13 @@ const char *gfdtd_last_error(void);
  *  lattice index.
  *  Initial state: all fields zero, or D^{1/2} = init_d and B^0 = init_b
  *  when given (E*^{1/2} then follows from them by (10c)).
+ *  Finite-duration modulation (GFDTD_FLAG_TIME_WINDOW, moving modulation
+ *  only): the moving profile exists only at node times t with
+ *  t_on <= t < t_off (E nodes at t = (n+1/2) S, H nodes at t = n S); at
+ *  other times every node sees the uniform background eps_bg, mu_bg.  D
+ *  and B carry over across the switches (temporal interfaces), which with
+ *  the moving boundaries form the corners of a space-time slab (the case
+ *  the footnote to the transfer-matrix method of App. B.3 sets apart).
  *  Source: soft source added to D at src_cell after (10b) of step n,
  *    src_amp * sin(src_omega (t - src_t0) + src_phase)
  *            * exp(-((t - src_t0)/src_tau)^2),  t = n S,
@@ -141,6 +150,9 @@ typedef struct gfdtd_problem {
     const double *init_d;        /* host, nz finite values, or NULL        */
     const double *init_b;        /* host, nz finite values (entry nz-1 is
                                     read on a ring only), or NULL          */
+    double t_on, t_off;          /* GFDTD_FLAG_TIME_WINDOW: not NaN (may be
+                                    infinite), else ignored                */
+    double eps_bg, mu_bg;        /* GFDTD_FLAG_TIME_WINDOW: > 0, finite    */
 } gfdtd_problem;
 
 /*

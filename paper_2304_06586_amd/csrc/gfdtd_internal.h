@@ -34,7 +34,7 @@ struct RunDesc {
     int32_t hr;            // halo lanes right of the owned lanes
     int32_t nprobe;
     int32_t abc;           // GFDTD_ABC_* (GFDTD_ABC_PERIODIC: a ring)
-    int32_t pad0;
+    int32_t windowed;      // finite-duration modulation (t_on, t_off)
     void *D[2];            // ping-pong D (run precision)
     void *B[2];            // ping-pong B
     const void *cE;        // E-node coefficient: S/eps' or S g mu'
@@ -45,6 +45,10 @@ struct RunDesc {
     const double *src;     // source samples, step n at [n-1]
     const int64_t *probes; // probe cells
     double *trace;         // nprobe * steps, probe q at row q
+    // finite-duration modulation: the profile exists for t_on <= t < t_off
+    double t_on, t_off;
+    double cEb, cHb;       // background coefficients S/eps_bg, S/mu_bg
+    double murB;           // background Mur coefficient (both ends)
 };
 
 struct TileRef {
@@ -94,7 +98,10 @@ hipError_t launch_zero(const PrepDesc *dev_descs, int count,
                        hipStream_t stream);
 hipError_t launch_init(const PrepDesc *dev_descs, int count, int64_t max_nz,
                        int precision, hipStream_t stream);
-hipError_t launch_tiles(int precision, int kind, bool ring, int C,
+// Steps the first ntiles tiles by one block.  win selects the kernel for
+// runs with a finite-duration modulation; each kernel skips the other's
+// runs, so a group holding both is stepped by two launches.
+hipError_t launch_tiles(int precision, int kind, bool ring, bool win, int C,
                         const RunDesc *runs, const TileRef *tiles, int64_t block,
                         int T, int ntiles, hipStream_t stream);
 

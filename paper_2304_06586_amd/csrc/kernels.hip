@@ -200,7 +200,7 @@ __device__ __forceinline__ R pick(const R (&a)[C], int idx)
 
 // ------------------------------------------------------------- the tile
 
-template <typename R, int C, int KIND, bool NEG, bool RING>
+template <typename R, int C, int KIND, bool NEG, bool RING, bool WIN>
 __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                                           int tile, int64_t block, int T)
 {
@@ -257,38 +257,86 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         load_cells<R, C>(Bsrc + kb, B);
     }
 
+    // Coefficient windows.  A window holds the coefficients of this lane's
+    // cells for a profile displaced by m cells (clamped to the grid, or
+    // wrapped on a ring); with a finite-duration modulation it holds the
+    // background coefficient while the profile is switched off.
+    R ce[C], ch[C], ge[C], gh[C];
+    auto load_e = [&](int m) __attribute__((always_inline)) {
+        if constexpr (RING) {
+            int64_t i = wrapi(kb - m, nz);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                ce[c] = cEp[i];
+                if constexpr (kMatter)
+                    ge[c] = gBp[i];
+                i = ring_next(i, nz);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t i = clampi(kb + c - m, 0, nz - 1);
+                ce[c] = cEp[i];
+                if constexpr (kMatter)
+                    ge[c] = gBp[i];
+            }
+        }
+    };
+    auto load_h = [&](int m) __attribute__((always_inline)) {
+        if constexpr (RING) {
+            int64_t i = wrapi(kb - m, nz);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                ch[c] = cHp[i];
+                if constexpr (kMatter)
+                    gh[c] = gBp[i];
+                i = ring_next(i, nz);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const int64_t i = clampi(kb + c - m, 0, nz - 2);
+                ch[c] = cHp[i];
+                if constexpr (kMatter)
+                    gh[c] = gBp[i];
+            }
+        }
+    };
+    // Finite-duration modulation (moving modulation only): whether the
+    // profile exists at node time tau S, and the background windows.
+    constexpr bool windowed = !kMatter && WIN;
+    const double S64 = rd->S;
+    auto active = [&](double tau) __attribute__((always_inline)) {
+        const double t = tau * S64;
+        return t >= rd->t_on && t < rd->t_off;
+    };
+    auto fill_e = [&]() __attribute__((always_inline)) {
+        const R v = (R)rd->cEb;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            ce[c] = v;
+    };
+    auto fill_h = [&]() __attribute__((always_inline)) {
+        const R v = (R)rd->cHb;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            ch[c] = v;
+    };
+
     // coefficients for the first step of the block: E nodes at n0-1/2,
     // H nodes at n0 (times exact in FP64).
     const int mE = profile_shift32(bS64, (double)n0 - 0.5);
     const int mH = profile_shift32(bS64, (double)n0);
-    R ce[C], ch[C], ge[C], gh[C];
-    if constexpr (RING) {
-        int64_t iE = wrapi(kb - mE, nz);
-        int64_t iH = wrapi(kb - mH, nz);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            ce[c] = cEp[iE];
-            ch[c] = cHp[iH];
-            if constexpr (kMatter) {
-                ge[c] = gBp[iE];
-                gh[c] = gBp[iH];
-            }
-            iE = ring_next(iE, nz);
-            iH = ring_next(iH, nz);
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int64_t iE = clampi(kb + c - mE, 0, nz - 1);
-            const int64_t iH = clampi(kb + c - mH, 0, nz - 2);
-            ce[c] = cEp[iE];
-            ch[c] = cHp[iH];
-            if constexpr (kMatter) {
-                ge[c] = gBp[iE];
-                gh[c] = gBp[iH];
-            }
-        }
-    }
+    if (windowed && !active((double)n0 - 0.5))
+        fill_e();
+    else
+        load_e(mE);
+    if (windowed && !active((double)n0))
+        fill_h();
+    else
+        load_h(mH);
+    (void)fill_e;
+    (void)fill_h;
 
     // a ring has no ends
     const bool touchL = !RING && x0 < 0;            // E node 0 (and ghosts)
@@ -418,10 +466,10 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     };
 
     // One time step n with fixed coefficient windows, from (Di, Bi) to
-    // (Dn, Bn); mEn is the profile shift at the E time n+1/2 (read by the
-    // end conditions only).
-    auto one_step = [&](auto edge_tag, int64_t n, int mEn, const R (&Di)[C],
-                        const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
+    // (Dn, Bn); mEn is the profile shift at the E time n+1/2 and onEn
+    // whether the profile exists then (read by the end conditions only).
+    auto one_step = [&](auto edge_tag, int64_t n, int mEn, bool onEn,
+                        const R (&Di)[C], const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
                         __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
         compute_es(Di, Bi);
@@ -499,7 +547,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int l0 = (int)(-x0 / C);
             if (lane == l0) {
                 if (abc == GFDTD_ABC_MUR1) {
-                    const R cL = (R)rd->murL[clampi(-mEn, 0, nz - 1)];
+                    const R cL = onEn ? (R)rd->murL[clampi(-mEn, 0, nz - 1)]
+                                      : (R)rd->murB;
                     Dn[0] = Di[1] + cL * (Dn[1] - Di[0]);
                 } else {
                     Dn[0] = (R)0;
@@ -512,7 +561,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int cr = (int)(r % C);
             const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
-            const R cR = (R)rd->murR[clampi(nz - 1 - mEn, 0, nz - 1)];
+            const R cR = onEn ? (R)rd->murR[clampi(nz - 1 - mEn, 0, nz - 1)]
+                              : (R)rd->murB;
             if (lane == lr) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
@@ -539,6 +589,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     auto steps_loop = [&](auto edge_tag) __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
         int mEc = mE;                       // E shift at the current n - 1/2
+        int mHc = mH;                       // H shift at the current n
         for (int s0 = 0; s0 < nsub; s0 += kWave) {
             const int len = nsub - s0 < kWave ? nsub - s0 : kWave;
             const int sl = s0 + lane;
@@ -549,9 +600,35 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                               profile_shift32(bS64, tn + 0.5) != profile_shift32(bS64, tn - 0.5);
             const uint64_t hmask = __ballot(hbit);
             const uint64_t emask = __ballot(ebit);
-            const uint64_t bmask = emask | (hmask >> 1);  // a move after step j
-            if (hmask & 1ull)
-                shift_h();
+            // finite-duration modulation: bit j of hsw / esw = the H / E
+            // window switches (on or off) before / after step j; hact /
+            // eact = the profile exists at the H time of step j / at the
+            // E time after it
+            uint64_t hsw = 0, esw = 0, hact = ~0ull, eact = ~0ull;
+            if constexpr (windowed) {
+                const bool aH = active(tn), aE = active(tn + 0.5);
+                hact = __ballot(aH);
+                eact = __ballot(aE);
+                hsw = __ballot(sl > 0 && sl < nsub && aH != active(tn - 1.0));
+                esw = __ballot(sl < nsub && aE != active(tn - 0.5));
+            }
+            // a move or switch after step j
+            const uint64_t bmask = emask | (hmask >> 1) | esw | (hsw >> 1);
+            auto update_h = [&](int q) __attribute__((always_inline)) {
+                if ((hmask >> q) & 1ull) {
+                    shift_h();
+                    mHc += dir;
+                }
+                if constexpr (windowed) {
+                    if ((hsw >> q) & 1ull) {
+                        if ((hact >> q) & 1ull)
+                            load_h(mHc);
+                        else
+                            fill_h();
+                    }
+                }
+            };
+            update_h(0);
             int j = 0;
             while (j < len) {
                 const uint64_t rest = bmask >> j;
@@ -561,13 +638,17 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 auto mEn_of = [&](int q) __attribute__((always_inline)) {
                     return mEc + (((emask >> q) & 1ull) ? dir : 0);
                 };
+                auto on_of = [&](int q) __attribute__((always_inline)) {
+                    return ((eact >> q) & 1ull) != 0;
+                };
                 int q = j;
                 for (; q + 1 <= stop; q += 2) {
-                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), D, B, D2, B2);
-                    one_step(edge_tag, n0 + s0 + q + 1, mEn_of(q + 1), D2, B2, D, B);
+                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), on_of(q), D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q + 1, mEn_of(q + 1), on_of(q + 1),
+                             D2, B2, D, B);
                 }
                 if (q <= stop) {
-                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), on_of(q), D, B, D2, B2);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         D[c] = D2[c];
@@ -578,8 +659,16 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                     shift_e();
                     mEc += dir;
                 }
-                if (stop + 1 < len && ((hmask >> (stop + 1)) & 1ull))
-                    shift_h();
+                if constexpr (windowed) {
+                    if ((esw >> stop) & 1ull) {
+                        if ((eact >> stop) & 1ull)
+                            load_e(mEc);
+                        else
+                            fill_e();
+                    }
+                }
+                if (stop + 1 < len)
+                    update_h(stop + 1);
                 j = stop + 1;
             }
         }
@@ -600,7 +689,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     }
 }
 
-template <typename R, int C, int KIND, bool RING>
+template <typename R, int C, int KIND, bool RING, bool WIN>
 __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
     const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
     int64_t block, int T, int ntiles)
@@ -611,13 +700,18 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
         return;
     const TileRef ref = tiles[t];
     const RunDesc *rd = runs + ref.run;
+    // Runs with a finite-duration modulation are stepped by the WIN
+    // kernel, the others by the plain one (each skips the other's tiles),
+    // so the plain kernel carries none of the window code.
+    if ((KIND != GFDTD_MATTER && rd->windowed != 0) != WIN)
+        return;
     if (rd->neg)
-        tile_body<R, C, KIND, true, RING>(rd, ref.tile, block, T);
+        tile_body<R, C, KIND, true, RING, WIN>(rd, ref.tile, block, T);
     else
-        tile_body<R, C, KIND, false, RING>(rd, ref.tile, block, T);
+        tile_body<R, C, KIND, false, RING, WIN>(rd, ref.tile, block, T);
 }
 
-template <typename R, int KIND, bool RING>
+template <typename R, int KIND, bool RING, bool WIN>
 static hipError_t launch_tiles_c(int C, const RunDesc *runs,
                                  const TileRef *tiles, int64_t block, int T,
                                  int ntiles, hipStream_t stream)
@@ -628,19 +722,19 @@ static hipError_t launch_tiles_c(int C, const RunDesc *runs,
     const dim3 blk(kWave * kWavesPerGroup);
     switch (C) {
     case 4:
-        hipLaunchKernelGGL((k_tiles<R, 4, KIND, RING>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 4, KIND, RING, WIN>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     case 8:
-        hipLaunchKernelGGL((k_tiles<R, 8, KIND, RING>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 8, KIND, RING, WIN>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     case 12:
-        hipLaunchKernelGGL((k_tiles<R, 12, KIND, RING>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 12, KIND, RING, WIN>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     case 16:
-        hipLaunchKernelGGL((k_tiles<R, 16, KIND, RING>), grid, blk, 0, stream, runs,
+        hipLaunchKernelGGL((k_tiles<R, 16, KIND, RING, WIN>), grid, blk, 0, stream, runs,
                            tiles, block, T, ntiles);
         break;
     default:
@@ -650,24 +744,30 @@ static hipError_t launch_tiles_c(int C, const RunDesc *runs,
 }
 
 template <typename R>
-static hipError_t launch_tiles_r(int kind, bool ring, int C, const RunDesc *runs,
-                                 const TileRef *tiles, int64_t block, int T,
-                                 int ntiles, hipStream_t stream)
+static hipError_t launch_tiles_r(int kind, bool ring, bool win, int C,
+                                 const RunDesc *runs, const TileRef *tiles,
+                                 int64_t block, int T, int ntiles, hipStream_t stream)
 {
-    if (kind == GFDTD_MATTER)
-        return ring ? launch_tiles_c<R, GFDTD_MATTER, true>(C, runs, tiles, block, T, ntiles, stream)
-                    : launch_tiles_c<R, GFDTD_MATTER, false>(C, runs, tiles, block, T, ntiles, stream);
-    return ring ? launch_tiles_c<R, GFDTD_MODULATION, true>(C, runs, tiles, block, T, ntiles, stream)
-                : launch_tiles_c<R, GFDTD_MODULATION, false>(C, runs, tiles, block, T, ntiles, stream);
+    if (kind == GFDTD_MATTER) {        // moving matter has no time window
+        if (win)
+            return hipSuccess;
+        return ring ? launch_tiles_c<R, GFDTD_MATTER, true, false>(C, runs, tiles, block, T, ntiles, stream)
+                    : launch_tiles_c<R, GFDTD_MATTER, false, false>(C, runs, tiles, block, T, ntiles, stream);
+    }
+    if (win)
+        return ring ? launch_tiles_c<R, GFDTD_MODULATION, true, true>(C, runs, tiles, block, T, ntiles, stream)
+                    : launch_tiles_c<R, GFDTD_MODULATION, false, true>(C, runs, tiles, block, T, ntiles, stream);
+    return ring ? launch_tiles_c<R, GFDTD_MODULATION, true, false>(C, runs, tiles, block, T, ntiles, stream)
+                : launch_tiles_c<R, GFDTD_MODULATION, false, false>(C, runs, tiles, block, T, ntiles, stream);
 }
 
-hipError_t launch_tiles(int precision, int kind, bool ring, int C,
+hipError_t launch_tiles(int precision, int kind, bool ring, bool win, int C,
                         const RunDesc *runs, const TileRef *tiles, int64_t block,
                         int T, int ntiles, hipStream_t stream)
 {
     if (precision == GFDTD_F32)
-        return launch_tiles_r<float>(kind, ring, C, runs, tiles, block, T, ntiles, stream);
-    return launch_tiles_r<double>(kind, ring, C, runs, tiles, block, T, ntiles, stream);
+        return launch_tiles_r<float>(kind, ring, win, C, runs, tiles, block, T, ntiles, stream);
+    return launch_tiles_r<double>(kind, ring, win, C, runs, tiles, block, T, ntiles, stream);
 }
 
 // ------------------------------------------------------------- set-up

@@ -109,6 +109,15 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
     for (int f = 0; f < p->nfreq; ++f)
         if (!std::isfinite(p->omegas[f]))
             return fail(GFDTD_E_INVALID, "omegas[%d] not finite", f);
+    if (p->flags & GFDTD_FLAG_TIME_WINDOW) {
+        if (p->kind != GFDTD_MODULATION)
+            return fail(GFDTD_E_UNSUPPORTED,
+                        "a time window applies to a moving modulation only");
+        if (std::isnan(p->t_on) || std::isnan(p->t_off))
+            return fail(GFDTD_E_INVALID, "t_on / t_off must not be NaN");
+        if (!finite_pos(p->eps_bg) || !finite_pos(p->mu_bg))
+            return fail(GFDTD_E_INVALID, "eps_bg / mu_bg must be finite and > 0");
+    }
     for (int64_t i = 0; i < p->nz; ++i)
         if ((p->init_d && !std::isfinite(p->init_d[i])) ||
             (p->init_b && !std::isfinite(p->init_b[i])))
@@ -192,6 +201,8 @@ gfdtd_status preflight(const gfdtd_problem *p, double *growth)
     std::vector<double> n2(p->nz);
     for (int64_t i = 0; i < p->nz; ++i)
         n2[i] = p->eps_rest[i] * p->mu_rest[i];
+    if (p->flags & GFDTD_FLAG_TIME_WINDOW)
+        n2.push_back(p->eps_bg * p->mu_bg);
     std::sort(n2.begin(), n2.end());
     n2.erase(std::unique(n2.begin(), n2.end()), n2.end());
     std::vector<double> pick;
@@ -409,6 +420,7 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         int64_t max_steps = 0, cells = 0;
         for (int i = 0; i < count; ++i)
             if (group_of(runs[i].p.precision, runs[i].p.kind, runs[i].p.abc) == g) {
+                G.has_window = G.has_window || (runs[i].p.flags & GFDTD_FLAG_TIME_WINDOW);
                 G.members.push_back(i);
                 max_steps = std::max(max_steps, runs[i].steps);
                 cells += runs[i].p.nz;
@@ -498,7 +510,7 @@ void Batch::count_launches()
     tiles_total = 0;
     for (auto &G : groups)
         for (int64_t b = 0; b < G.nblocks; ++b) {
-            launches += 1;
+            launches += G.has_window ? 2 : 1;
             tiles_total += live_tiles(G, b);
         }
 }
@@ -622,10 +634,13 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                                (double)std::min<int64_t>(T, r.steps - b * (int64_t)T);
                     }
                 auto launch = [&](int64_t b) {
-                    return launch_tiles(G.precision, G.kind, G.ring, C,
-                                        reinterpret_cast<const RunDesc *>(ws + G.runs_off),
-                                        reinterpret_cast<const TileRef *>(ws + G.tiles_off),
-                                        b, T, live_tiles(G, b), stream);
+                    hipError_t le = hipSuccess;
+                    for (int w = 0; w < (G.has_window ? 2 : 1) && !le; ++w)
+                        le = launch_tiles(G.precision, G.kind, G.ring, w == 1, C,
+                                          reinterpret_cast<const RunDesc *>(ws + G.runs_off),
+                                          reinterpret_cast<const TileRef *>(ws + G.tiles_off),
+                                          b, T, live_tiles(G, b), stream);
+                    return le;
                 };
                 if ((e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + G.prep_off),
                                      (int)G.members.size(), G.max_field, G.precision,
@@ -716,6 +731,16 @@ void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
     rd.hr = hr;
     rd.nprobe = p.nprobe;
     rd.abc = p.abc;
+    rd.windowed = (p.flags & GFDTD_FLAG_TIME_WINDOW) ? 1 : 0;
+    if (rd.windowed) {
+        rd.t_on = p.t_on;
+        rd.t_off = p.t_off;
+        rd.cEb = p.courant / p.eps_bg;
+        rd.cHb = p.courant / p.mu_bg;
+        // background Mur coefficient (S u - 1)/(S u + 1), u = 1/n
+        const double u = 1.0 / std::sqrt(p.eps_bg * p.mu_bg);
+        rd.murB = (p.courant * u - 1.0) / (p.courant * u + 1.0);
+    }
     for (int f = 0; f < 2; ++f) {
         rd.D[f] = base + r.L.field[f] + kPad * w;
         rd.B[f] = base + r.L.field[2 + f] + kPad * w;
@@ -812,12 +837,14 @@ gfdtd_status Batch::enqueue_steps(hipStream_t s)
         for (auto &G : groups) {
             if (b >= G.nblocks)
                 continue;
-            hipError_t e = launch_tiles(G.precision, G.kind, G.ring, G.C,
-                                        reinterpret_cast<const RunDesc *>(ws + G.runs_off),
-                                        reinterpret_cast<const TileRef *>(ws + G.tiles_off),
-                                        b, G.T, live_tiles(G, b), s);
-            if (e)
-                return hip_fail(e, "launch step kernel");
+            for (int w = 0; w < (G.has_window ? 2 : 1); ++w) {
+                hipError_t e = launch_tiles(G.precision, G.kind, G.ring, w == 1, G.C,
+                                            reinterpret_cast<const RunDesc *>(ws + G.runs_off),
+                                            reinterpret_cast<const TileRef *>(ws + G.tiles_off),
+                                            b, G.T, live_tiles(G, b), s);
+                if (e)
+                    return hip_fail(e, "launch step kernel");
+            }
         }
     return GFDTD_OK;
 }

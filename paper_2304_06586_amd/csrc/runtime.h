@@ -76,6 +76,7 @@ gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *
 struct Group {
     int precision = 0, kind = 0, C = 16, T = 16;
     bool ring = false;                // periodic ends
+    bool has_window = false;          // holds finite-duration modulations
     std::vector<int> members;         // run indices, longest first
     std::vector<int64_t> blocks_of;   // blocks per member
     std::vector<int64_t> tiles_prefix;

@@ -207,6 +207,7 @@ struct Server {
     int cur[kGroups] = {};           // table buffer in use, per group
     size_t runs_off[2][kGroups], tiles_off[2][kGroups];
     int ntiles[kGroups] = {};
+    int nwin[kGroups] = {};          // live requests with a time window
     Pinned stage[2][kGroups];        // host staging of the table buffers
     hipEvent_t stage_ev[2][kGroups] = {};
     bool stage_used[2][kGroups] = {};
@@ -343,6 +344,8 @@ struct Server {
             rq->end_block = gblock + (rq->r.steps + T - 1) / T - 1;
             live.push_back(rq->id);
             ntiles[rq->group] += (int)rq->ntiles;
+            if (rq->r.p.flags & GFDTD_FLAG_TIME_WINDOW)
+                nwin[rq->group] += 1;
             gdirty[rq->group] = true;
             hipStream_t st = gs[rq->group >> 1];
             // memory released by retirements on other streams is reused
@@ -532,6 +535,8 @@ struct Server {
         rq->state = RETIRING;
         pool.release(rq->off - tables_bytes, rq->bytes);
         ntiles[rq->group] -= (int)rq->ntiles;
+        if (rq->r.p.flags & GFDTD_FLAG_TIME_WINDOW)
+            nwin[rq->group] -= 1;
         live.erase(std::find(live.begin(), live.end(), rq->id));
         gdirty[rq->group] = true;
         return GFDTD_OK;
@@ -578,12 +583,14 @@ struct Server {
                     if (!ntiles[g])
                         continue;
                     const int pr = group_precision(g);
-                    e = launch_tiles(pr, group_kind(g), group_ring(g), Cg[pr],
-                                     reinterpret_cast<const RunDesc *>(pool_base + runs_off[cur[g]][g]),
-                                     reinterpret_cast<const TileRef *>(pool_base + tiles_off[cur[g]][g]),
-                                     gblock, T, ntiles[g], gs[g >> 1]);
-                    if (e)
-                        return hip_fail(e, "launch step kernel");
+                    for (int w = 0; w < (nwin[g] ? 2 : 1); ++w) {
+                        e = launch_tiles(pr, group_kind(g), group_ring(g), w == 1, Cg[pr],
+                                         reinterpret_cast<const RunDesc *>(pool_base + runs_off[cur[g]][g]),
+                                         reinterpret_cast<const TileRef *>(pool_base + tiles_off[cur[g]][g]),
+                                         gblock, T, ntiles[g], gs[g >> 1]);
+                        if (e)
+                            return hip_fail(e, "launch step kernel");
+                    }
                 }
             left -= (int32_t)nb;
             for (size_t i = 0; i < live.size();) {

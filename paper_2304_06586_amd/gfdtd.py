@@ -8,7 +8,8 @@ path: if the native library is missing the calls raise.
 Problem descriptors are duck-typed: any object with the attributes of
 `workloads.Problem` (nz, steps, courant, beta, kind, precision, abc,
 flags, eps_rest, mu_rest, src_cell, pulse.{amp, omega, t0, tau, phase,
-t_off}, probes, omegas, and optionally init_d / init_b).
+t_off}, probes, omegas, and optionally init_d / init_b and window
+(t_on, t_off, eps_bg, mu_bg)).
 """
 from __future__ import annotations
 
@@ -41,6 +42,7 @@ GFDTD_ABC_PERIODIC = 2
 GFDTD_FLAG_RECORD_TRACE = 1
 GFDTD_FLAG_ALLOW_UNSTABLE = 2
 GFDTD_FLAG_KEEP_FIELDS = 4
+GFDTD_FLAG_TIME_WINDOW = 8
 GFDTD_VARIANT_AUTO = 0
 GFDTD_VARIANT_STEP = 1
 GFDTD_VARIANT_TILED = 2
@@ -61,6 +63,8 @@ class gfdtd_problem(C.Structure):
         ("src_phase", C.c_double), ("src_t_off", C.c_double),
         ("probe_cells", _PI64), ("omegas", _PD),
         ("init_d", _PD), ("init_b", _PD),
+        ("t_on", C.c_double), ("t_off", C.c_double),
+        ("eps_bg", C.c_double), ("mu_bg", C.c_double),
     ]
 
 
@@ -194,6 +198,11 @@ class _Marshalled:
         s.precision = int(p.precision)
         s.abc = int(p.abc)
         s.flags = int(p.flags)
+        win = getattr(p, "window", None)
+        if win is not None:
+            s.flags |= GFDTD_FLAG_TIME_WINDOW
+            s.t_on, s.t_off = float(win.t_on), float(win.t_off)
+            s.eps_bg, s.mu_bg = float(win.eps_bg), float(win.mu_bg)
         s.nprobe = self.nprobe
         s.nfreq = self.nfreq
         s.nz = self.nz

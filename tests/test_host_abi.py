@@ -50,7 +50,7 @@ def test_struct_sizes_match_header(P):
     """The ctypes layouts match the C structs (the library rejects a
     smaller struct_size, so a mismatch would show as E_INVALID)."""
     g = P.gfdtd
-    assert ctypes.sizeof(g.gfdtd_problem) == 4 * 8 + 8 * 3 + 8 * 2 + 8 + 6 * 8 + 8 * 4
+    assert ctypes.sizeof(g.gfdtd_problem) == 4 * 8 + 8 * 3 + 8 * 2 + 8 + 6 * 8 + 8 * 4 + 8 * 4
     assert ctypes.sizeof(g.gfdtd_result) == 8 + 8 + 5 * 8
     assert ctypes.sizeof(g.gfdtd_exec) == 24
     assert ctypes.sizeof(g.gfdtd_stats) == 16 + 16 + 24
@@ -167,3 +167,26 @@ def test_benchmark_configs_pass_preflight(P):
     for p in W.crystal_runs(0, count=64):
         P.gfdtd_check(p)
     P.gfdtd_check(W.gradient_run(0, downscaled=True))
+
+
+def test_time_window_validated_and_in_the_preflight(P):
+    """A finite-duration window needs a moving modulation, a finite
+    positive background and non-NaN switch times; the background medium
+    enters the stability pre-flight."""
+    p = W.small_case(200, 100, 0.3, seed=0, structure="uniform")
+    p = p.replace(eps_rest=np.full(200, 2.0), mu_rest=np.ones(200))
+    P.gfdtd_check(p.replace(window=W.TimeWindow(5.0, float("inf"), 1.0, 1.0)))
+    for win in (W.TimeWindow(float("nan"), 9.0, 1.0, 1.0),
+                W.TimeWindow(0.0, 9.0, 0.0, 1.0),
+                W.TimeWindow(0.0, 9.0, 1.0, float("inf"))):
+        with pytest.raises(P.GfdtdError) as e:
+            P.gfdtd_check(p.replace(window=win))
+        assert e.value.status == P.gfdtd.GFDTD_E_INVALID
+    with pytest.raises(P.GfdtdError) as e:
+        P.gfdtd_check(W.small_case(200, 100, 0.3, kind=W.MATTER, seed=0)
+                      .replace(window=W.TimeWindow(0.0, 9.0, 1.0, 1.0)))
+    assert e.value.status == P.gfdtd.GFDTD_E_UNSUPPORTED
+    # beta n = 0.3 * 4 > 1 for the background alone: unstable
+    with pytest.raises(P.GfdtdError) as e:
+        P.gfdtd_check(p.replace(window=W.TimeWindow(0.0, 9.0, 16.0, 1.0)))
+    assert e.value.status == P.gfdtd.GFDTD_E_UNSTABLE
