@@ -302,7 +302,10 @@ typedef struct gfdtd_server_config {
     uint32_t struct_size;
     int32_t max_slots;           /* admitted runs at once, >= 1            */
     int32_t block_steps;         /* steps per progress block (0 = auto)    */
-    int32_t reserved0;
+    int32_t max_ahead;           /* blocks enqueued beyond the last block
+                                    the GPU has finished, at most (0 = 8):
+                                    bounds how long a new request waits
+                                    behind work already enqueued           */
     void *pool;                  /* device memory for run state            */
     size_t pool_bytes;           /* the HBM budget                         */
     void *stream;
@@ -318,9 +321,10 @@ gfdtd_status gfdtd_server_submit(gfdtd_server *s, const gfdtd_problem *p,
                                  int64_t steps, uint64_t *id);
 /* Admit what fits, enqueue up to max_blocks progress blocks on the stream
  * and retire the runs whose last block is enqueued (their DFT and result
- * copies are enqueued too).  Returns without waiting for the GPU.  *live
- * gets the number of admitted runs afterwards, *queued the waiting ones
- * (either may be NULL). */
+ * copies are enqueued too).  Returns without waiting for the GPU; enqueues
+ * fewer blocks (possibly none) once max_ahead blocks are outstanding, so a
+ * serving loop calls it repeatedly.  *live gets the number of admitted runs
+ * afterwards, *queued the waiting ones (either may be NULL). */
 gfdtd_status gfdtd_server_progress(gfdtd_server *s, int32_t max_blocks,
                                    int32_t *live, int32_t *queued);
 /* GFDTD_E_NOT_READY until the request has finished.  With out == NULL,

@@ -208,6 +208,56 @@ struct Server {
     size_t runs_off[2][kGroups], tiles_off[2][kGroups];
     int ntiles[kGroups] = {};
     int nwin[kGroups] = {};          // live requests with a time window
+    // run-ahead tracking: events recorded on every group stream after each
+    // run of block launches, with the global block count reached
+    struct Inflight {
+        int64_t gblock_end;
+        hipEvent_t ev[4];
+    };
+    std::deque<Inflight> inflight;
+    std::vector<hipEvent_t> spare_ev;
+    int64_t done_block = 0;          // blocks below this have finished
+    int max_ahead = 8;
+
+    gfdtd_status mark_inflight()
+    {
+        Inflight f;
+        f.gblock_end = gblock;
+        for (int k = 0; k < 4; ++k) {
+            hipError_t e;
+            if (spare_ev.empty()) {
+                hipEvent_t ev;
+                if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)))
+                    return hip_fail(e, "create events");
+                spare_ev.push_back(ev);
+            }
+            f.ev[k] = spare_ev.back();
+            spare_ev.pop_back();
+            if ((e = hipEventRecord(f.ev[k], gs[k])))
+                return hip_fail(e, "record progress");
+        }
+        inflight.push_back(f);
+        return GFDTD_OK;
+    }
+
+    gfdtd_status reap()
+    {
+        while (!inflight.empty()) {
+            Inflight &f = inflight.front();
+            for (int k = 0; k < 4; ++k) {
+                const hipError_t e = hipEventQuery(f.ev[k]);
+                if (e == hipErrorNotReady)
+                    return GFDTD_OK;
+                if (e != hipSuccess)
+                    return hip_fail(e, "query progress");
+            }
+            done_block = f.gblock_end;
+            for (int k = 0; k < 4; ++k)
+                spare_ev.push_back(f.ev[k]);
+            inflight.pop_front();
+        }
+        return GFDTD_OK;
+    }
     Pinned stage[2][kGroups];        // host staging of the table buffers
     hipEvent_t stage_ev[2][kGroups] = {};
     bool stage_used[2][kGroups] = {};
@@ -229,6 +279,11 @@ struct Server {
                 (void)hipStreamDestroy(s);
         if (fork_ev)
             (void)hipEventDestroy(fork_ev);
+        for (auto &f : inflight)
+            for (hipEvent_t e : f.ev)
+                (void)hipEventDestroy(e);
+        for (hipEvent_t e : spare_ev)
+            (void)hipEventDestroy(e);
     }
 
     gfdtd_status create(const gfdtd_server_config *cfg)
@@ -250,6 +305,9 @@ struct Server {
         // tiles and deeper blocks lowered throughput and raised latency).
         Cg[0] = Cg[1] = 8;
         T = cfg->block_steps > 0 ? cfg->block_steps : 24;
+        if (cfg->max_ahead < 0)
+            return fail(GFDTD_E_INVALID, "max_ahead must be >= 0");
+        max_ahead = cfg->max_ahead > 0 ? cfg->max_ahead : 8;
         // two copies of the run and tile tables at the front of the pool;
         // a tile stores at least 64 cells and a run costs more than 32
         // bytes per cell, which bounds the tiles the pool can hold
@@ -577,7 +635,16 @@ struct Server {
             int64_t next_end = INT64_MAX;
             for (uint64_t id : live)
                 next_end = std::min(next_end, reqs[id]->end_block);
-            const int64_t nb = std::min<int64_t>(next_end - gblock + 1, left);
+            // run-ahead limit: at most max_ahead blocks enqueued beyond the
+            // last block the GPU has finished (a request admitted now then
+            // waits behind at most that many)
+            if ((st = reap()) != GFDTD_OK)
+                return st;
+            const int64_t room = (int64_t)max_ahead - (gblock - done_block);
+            if (room <= 0)
+                break;
+            const int64_t nb = std::min<int64_t>(std::min<int64_t>(next_end - gblock + 1, left),
+                                                 room);
             for (int64_t b = 0; b < nb; ++b, ++gblock)
                 for (int g = 0; g < kGroups; ++g) {
                     if (!ntiles[g])
@@ -593,6 +660,8 @@ struct Server {
                     }
                 }
             left -= (int32_t)nb;
+            if ((st = mark_inflight()) != GFDTD_OK)
+                return st;
             for (size_t i = 0; i < live.size();) {
                 Request *rq = reqs[live[i]].get();
                 if (rq->end_block < gblock) {

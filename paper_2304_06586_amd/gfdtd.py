@@ -97,7 +97,7 @@ class gfdtd_stats(C.Structure):
 class gfdtd_server_config(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("max_slots", C.c_int32),
-        ("block_steps", C.c_int32), ("reserved0", C.c_int32),
+        ("block_steps", C.c_int32), ("max_ahead", C.c_int32),
         ("pool", C.c_void_p), ("pool_bytes", C.c_size_t),
         ("stream", C.c_void_p),
     ]
@@ -442,7 +442,7 @@ class Server:
     """gfdtd_server_create / submit / progress / poll / destroy."""
 
     def __init__(self, pool_bytes: int, max_slots: int = 256, block_steps: int = 0,
-                 stream=None):
+                 stream=None, max_ahead: int = 0):
         import torch
         self._lib = load_library()
         self.stream = torch.cuda.current_stream() if stream is None else stream
@@ -451,6 +451,7 @@ class Server:
         cfg.struct_size = C.sizeof(gfdtd_server_config)
         cfg.max_slots = int(max_slots)
         cfg.block_steps = int(block_steps)
+        cfg.max_ahead = int(max_ahead)
         cfg.pool = C.c_void_p(self._pool.data_ptr())
         cfg.pool_bytes = int(pool_bytes)
         cfg.stream = _stream_handle(self.stream)
