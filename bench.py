@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tiling instead of autotuning it")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-tmm", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-loads", default="0.5,0.8",
                     help="offered loads as fractions of the saturated request "
@@ -340,6 +341,36 @@ def main():
                 log(f"plain {key}: {plain[key]['value']:.4g} cell-updates/s "
                     f"(C={pst['cells_per_lane']}, T={pst['block_steps']})")
 
+    # ------------------------------------------- transfer-matrix sweep (GPU)
+    tmm = None
+    if not args.no_tmm:
+        stacks, omegas = W.tmm_crystals(args.seed, 4096, nomega=256)
+        layers = sum(len(s.eps) for s in stacks)
+        P.gfdtd_tmm(stacks[:8], omegas[:8])               # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Tg, Gg = P.gfdtd_tmm(stacks, omegas)
+        dt = time.perf_counter() - t0
+        evals = len(stacks) * len(omegas)
+        tmm = {"stack_frequency_evals_per_s": evals / dt,
+               "layer_evals_per_s": layers * len(omegas) / dt,
+               "ms": dt * 1e3, "stacks": len(stacks), "frequencies": len(omegas),
+               "layers": layers,
+               "note": "one synchronous gfdtd_tmm call, host-to-device upload of "
+                       "the stacks and result copies included; FP64"}
+        if not args.no_cpu:
+            from oracle import analytic as A
+            sub = stacks[:4]
+            om = omegas[::32]
+            c0 = time.perf_counter()
+            for s in sub:
+                for w in om:
+                    A.transfer_matrix(w, list(s.eps), list(s.widths), s.beta)
+            cdt = time.perf_counter() - c0
+            tmm["cpu_oracle_stack_frequency_evals_per_s"] = len(sub) * len(om) / cdt
+        log(f"transfer-matrix sweep: {tmm['stack_frequency_evals_per_s']:.4g} "
+            f"(stack, omega) evaluations/s, {tmm['layer_evals_per_s']:.4g} layers/s")
+
     # ---------------------------------------- error and CPU baseline (sample)
     sample = [q.replace(steps=min(q.steps, args.cpu_sample_steps))
               for q in W.crystal_runs(args.seed, count=args.cpu_sample_runs,
@@ -396,6 +427,7 @@ def main():
         "batched_f64": batched_f64,
         "serving": serving,
         "plain": plain,
+        "tmm_sweep": tmm,
         "error": error,
         "cpu_baseline": cpu,
     }

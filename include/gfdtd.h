@@ -334,6 +334,42 @@ gfdtd_status gfdtd_server_progress(gfdtd_server *s, int32_t max_blocks,
 gfdtd_status gfdtd_server_poll(gfdtd_server *s, uint64_t id, gfdtd_result *out);
 void gfdtd_server_destroy(gfdtd_server *s);
 
+/* ------------------------------------------------ transfer-matrix sweeps */
+/*
+ * Frequency-domain scattering of moving multilayers by the transfer-matrix
+ * method of App. B.3, batched over stacks and frequencies: the closed-form
+ * companion of the time-domain solver for parameter sweeps (uniform
+ * space-time slabs only).  Layers 0..N-1 all move at beta; layers 0 and N-1
+ * are semi-infinite and the wave is incident from layer 0 at lab angular
+ * frequency omega.  Within layer m (index n_m = sqrt(eps mu), impedance
+ * eta_m = sqrt(mu/eps)) the forward and backward waves have the Doppler
+ * frequencies omega (1 - n_0 beta)/(1 -/+ n_m beta) (the phase invariant
+ * of a moving boundary); interfaces match E* and H* (the star amplitudes).
+ * For each (stack, omega) the lab-frame E-field transmission T (layer N-1)
+ * and reflection Gamma (layer 0) are returned.  All in FP64.
+ */
+typedef struct gfdtd_tmm_stack {
+    uint32_t struct_size;
+    int32_t nlayers;             /* N >= 2                                 */
+    double beta;                 /* |beta| n_m < 1 in every layer          */
+    const double *eps;           /* host, N values > 0                     */
+    const double *mu;            /* host, N values > 0, or NULL for all 1  */
+    const double *widths;        /* host, N-2 lab-frame widths >= 0 of the
+                                    inner layers (NULL if N == 2)          */
+} gfdtd_tmm_stack;
+
+/* Device workspace for gfdtd_tmm. */
+gfdtd_status gfdtd_tmm_workspace_bytes(const gfdtd_tmm_stack *stacks,
+                                       int32_t nstacks, int32_t nomega,
+                                       size_t *bytes);
+/* Evaluate every stack at every omega (host array, nomega finite values).
+ * t and gamma are caller-allocated host arrays of 2 * nstacks * nomega
+ * doubles, (re, im) pairs, stack-major: entry [s][f].  Synchronous.
+ * GFDTD_E_INVALID for a malformed stack (it names the stack). */
+gfdtd_status gfdtd_tmm(const gfdtd_tmm_stack *stacks, int32_t nstacks,
+                       const double *omegas, int32_t nomega, void *ws,
+                       size_t ws_bytes, void *stream, double *t, double *gamma);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,7 +100,12 @@ def transfer_matrix(omega: float, eps: Sequence[float], widths: Sequence[float],
     def K(m):
         return np.array([[1.0, 1.0], [1.0 / eta[m], -1.0 / eta[m]]], dtype=complex)
 
+    # det M is carried as the product of the factors' determinants (det of
+    # a product is the product of dets): forming it from the entries of M
+    # cancels catastrophically when M grows, as in the stopband of a long
+    # crystal.  det(K(m+1)^-1 K(m)) = eta_{m+1}/eta_m.
     M = np.eye(2, dtype=complex)
+    det = 1.0 + 0.0j
     for m in range(N - 1):
         if m >= 1:
             wp = inv / (1.0 - n[m] * beta)
@@ -108,9 +113,11 @@ def transfer_matrix(omega: float, eps: Sequence[float], widths: Sequence[float],
             P = np.diag([np.exp(1j * n[m] * wp * widths[m - 1]),
                          np.exp(-1j * n[m] * wm * widths[m - 1])])
             M = P @ M
+            det *= P[0, 0] * P[1, 1]
         M = np.linalg.solve(K(m + 1), K(m)) @ M
+        det *= eta[m + 1] / eta[m]
     r_star = -M[1, 0] / M[1, 1]
-    t_star = (M[0, 0] * M[1, 1] - M[0, 1] * M[1, 0]) / M[1, 1]
+    t_star = det / M[1, 1]
     G = r_star * (1.0 - n[0] * beta) / (1.0 + n[0] * beta)
     T = t_star * (1.0 - n[0] * beta) / (1.0 - n[-1] * beta)
     return complex(T), complex(G)

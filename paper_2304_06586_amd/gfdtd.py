@@ -113,6 +113,13 @@ class GfdtdError(RuntimeError):
 _lib = None
 _lock = threading.Lock()
 
+class gfdtd_tmm_stack(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("nlayers", C.c_int32), ("beta", C.c_double),
+        ("eps", _PD), ("mu", _PD), ("widths", _PD),
+    ]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "gfdtd_status_str": (C.c_char_p, [C.c_int]),
@@ -145,6 +152,10 @@ EXPORTS = {
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gfdtd_server_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(gfdtd_result)]),
     "gfdtd_server_destroy": (None, [C.c_void_p]),
+    "gfdtd_tmm_workspace_bytes": (C.c_int, [C.POINTER(gfdtd_tmm_stack), C.c_int32,
+                                            C.c_int32, C.POINTER(C.c_size_t)]),
+    "gfdtd_tmm": (C.c_int, [C.POINTER(gfdtd_tmm_stack), C.c_int32, _PD, C.c_int32,
+                            C.c_void_p, C.c_size_t, C.c_void_p, _PD, _PD]),
 }
 
 
@@ -366,6 +377,47 @@ def gfdtd_solve_batch(problems: Sequence, steps=None, stream=None,
     for o, r in zip(outs, res):
         o.struct = r
     return [o.as_dict() for o in outs]
+
+
+def _tmm_structs(stacks):
+    keep = []
+    arr = (gfdtd_tmm_stack * max(1, len(stacks)))()
+    for i, st in enumerate(stacks):
+        eps = np.ascontiguousarray(st.eps, dtype=np.float64)
+        mu = None if st.mu is None else np.ascontiguousarray(st.mu, dtype=np.float64)
+        widths = np.ascontiguousarray(st.widths, dtype=np.float64)
+        if mu is not None and mu.shape != eps.shape:
+            raise ValueError("mu must have one value per layer")
+        if widths.shape != (max(len(eps) - 2, 0),):
+            raise ValueError("widths must hold the inner layers' widths")
+        keep += [eps, mu, widths]
+        a = arr[i]
+        a.struct_size = C.sizeof(gfdtd_tmm_stack)
+        a.nlayers = len(eps)
+        a.beta = float(st.beta)
+        a.eps = eps.ctypes.data_as(_PD)
+        a.mu = mu.ctypes.data_as(_PD) if mu is not None else None
+        a.widths = widths.ctypes.data_as(_PD) if len(widths) else None
+    return arr, keep
+
+
+def gfdtd_tmm(stacks: Sequence, omegas, stream=None):
+    """Transfer-matrix (T, Gamma) of every stack (objects with eps, mu
+    (or None), widths, beta) at every angular frequency: two complex arrays
+    of shape (len(stacks), len(omegas))."""
+    lib = load_library()
+    arr, keep = _tmm_structs(stacks)
+    om = np.ascontiguousarray(omegas, dtype=np.float64)
+    n = C.c_size_t(0)
+    _check(lib.gfdtd_tmm_workspace_bytes(arr, len(stacks), len(om), C.byref(n)))
+    ws = _device_buffer(n.value)
+    t = np.zeros((len(stacks), len(om), 2))
+    g = np.zeros((len(stacks), len(om), 2))
+    _check(lib.gfdtd_tmm(arr, len(stacks), om.ctypes.data_as(_PD), len(om),
+                         C.c_void_p(ws.data_ptr()), n.value, _stream_handle(stream),
+                         t.ctypes.data_as(_PD), g.ctypes.data_as(_PD)))
+    del keep
+    return t[..., 0] + 1j * t[..., 1], g[..., 0] + 1j * g[..., 1]
 
 
 class Batch:

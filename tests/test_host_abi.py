@@ -190,3 +190,30 @@ def test_time_window_validated_and_in_the_preflight(P):
     with pytest.raises(P.GfdtdError) as e:
         P.gfdtd_check(p.replace(window=W.TimeWindow(0.0, 9.0, 16.0, 1.0)))
     assert e.value.status == P.gfdtd.GFDTD_E_UNSTABLE
+
+
+def test_tmm_stacks_validated(P):
+    """gfdtd_tmm_workspace_bytes validates every stack on the host: layer
+    count, |beta| < 1 and |beta| n < 1 in each layer, positive media and
+    non-negative widths."""
+    import ctypes as C
+    g = P.gfdtd
+    lib = P.load_library()
+
+    def check(stacks):
+        arr, keep = g._tmm_structs(stacks)
+        n = C.c_size_t(0)
+        return lib.gfdtd_tmm_workspace_bytes(arr, len(stacks), 8, C.byref(n)), n.value
+
+    ok = W.TmmStack(eps=np.array([1.0, 4.0, 1.0]), widths=np.array([10.0]), beta=0.3)
+    st, n = check([ok])
+    assert st == 0 and n > 0
+    bad = [W.TmmStack(eps=np.array([1.0]), widths=np.zeros(0), beta=0.1),
+           W.TmmStack(eps=np.array([1.0, 4.0, 1.0]), widths=np.array([-1.0]), beta=0.1),
+           W.TmmStack(eps=np.array([1.0, 16.0, 1.0]), widths=np.array([5.0]), beta=0.3),
+           W.TmmStack(eps=np.array([1.0, 0.0]), widths=np.zeros(0), beta=0.1),
+           W.TmmStack(eps=np.array([1.0, 2.0]), widths=np.zeros(0), beta=1.0)]
+    for b in bad:
+        st, _ = check([ok, b])
+        assert st == g.GFDTD_E_INVALID
+        assert "stack 1" in g.load_library().gfdtd_last_error().decode()

@@ -160,3 +160,21 @@ def test_matter_speed_is_relativistic_addition():
         c1 = np.sum(ts * e1 ** 2) / np.sum(e1 ** 2)
         speed = 2000.0 / (c1 - c0)
         assert abs(speed - want) < 0.01 * want
+
+
+def test_transfer_matrix_conserves_energy_in_long_stationary_crystals():
+    """At v = 0 a lossless stack between two vacuum half-spaces conserves
+    energy, |Gamma|^2 + |T|^2 = 1, at every frequency -- also deep in the
+    stopband of a long high-contrast crystal, where the entries of the
+    total matrix grow by many orders of magnitude (the transmission comes
+    from det M / M22 with det M carried factor by factor)."""
+    from oracle import analytic as A
+    rng = np.random.default_rng(5)
+    for _ in range(6):
+        e1, e2 = rng.uniform(1.0, 12.0, size=2)
+        P = int(rng.integers(40, 100))
+        eps = [1.0] + [e1, e2] * P + [1.0]
+        widths = [13.0, 21.0] * P
+        for w in np.linspace(0.05, 0.9, 23):
+            T, G = A.transfer_matrix(w, eps, widths, 0.0)
+            assert abs(abs(G) ** 2 + abs(T) ** 2 - 1.0) < 1e-9, (e1, e2, P, w)

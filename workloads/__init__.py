@@ -492,3 +492,42 @@ def dispersion_runs(points, steps: int, precision: int = F64) -> List[Problem]:
         runs.append(Problem(**base, init_d=cd, init_b=zero, label=f"disp{i}_d"))
         runs.append(Problem(**base, init_d=zero, init_b=cb, label=f"disp{i}_b"))
     return runs
+
+
+# --------------------------------------------------------------------------
+# Transfer-matrix sweeps (App. B.3): uniform moving multilayers in the
+# frequency domain
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class TmmStack:
+    """Layers 0..N-1 moving at beta (0 and N-1 semi-infinite); widths of
+    the inner layers in cells (lab frame)."""
+    eps: np.ndarray
+    widths: np.ndarray
+    beta: float
+    mu: Optional[np.ndarray] = None
+
+
+def tmm_crystals(seed: int, count: int, nomega: int = 256
+                 ) -> Tuple[List[TmmStack], np.ndarray]:
+    """Seeded bilayer crystals in vacuum, drawn like the batched FDTD
+    crystals: eps1, eps2 ~ U[1, 12], period p ~ U{16..128} cells split in
+    half, P ~ U{5..100} periods, beta ~ U[-0.9, 0.9] redrawn while
+    |beta| sqrt(max eps) > 0.98; and nomega angular frequencies spread over
+    [0.2, 3] omega0 (omega0 = 2 pi / 40)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        e1, e2 = (float(x) for x in rng.uniform(1.0, 12.0, size=2))
+        p = int(rng.integers(16, 129))
+        P = int(rng.integers(5, 101))
+        beta = float(rng.uniform(-0.9, 0.9))
+        nmax = math.sqrt(max(e1, e2))
+        while abs(beta) * nmax > LUMINAL_MARGIN:
+            beta = float(rng.uniform(-0.9, 0.9))
+        eps = np.array([1.0] + [e1, e2] * P + [1.0])
+        widths = np.array([p // 2, p - p // 2] * P, dtype=np.float64)
+        out.append(TmmStack(eps=eps, widths=widths, beta=beta))
+    omega0 = 2.0 * math.pi / LAMBDA0
+    return out, np.linspace(0.2 * omega0, 3.0 * omega0, nomega)
