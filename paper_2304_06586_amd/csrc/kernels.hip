@@ -224,6 +224,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     // S-scaled coefficients.
     const R bS = (R)bS64;
     const R hb = (R)rd->hb;             // S beta / 2
+    const R k1 = (R)(bS64 - rd->hb);    // weights of the folded updates
+    const R k2 = (R)(-rd->hb);
     const int hl = rd->hl;
     const int hr = rd->hr;
     const int abc = rd->abc;
@@ -472,23 +474,50 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                         const R (&Di)[C], const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
                         __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
-        compute_es(Di, Bi);
-        if constexpr (kEdge)
-            record(n);
 
         // (10a) Faraday with the Table 1 dB/dz, in telescoped form:
         //   P_k = E~_k + bS B_up(k),  B' = B + (P_k - P_{k+1}),
         // B_up(k) = B_{k-1} (column a) or B_k (column b).  A uniform field
-        // stays exactly uniform.
-        R P[C], Hs[C];
+        // stays exactly uniform.  For a moving modulation E~ (10c) is
+        // folded in: P_k = cE D_k + (bS - hb) B_1 - hb B_2 with
+        // (B_1, B_2) = (B_{k-1}, B_{k-2}) in column a, (B_k, B_{k+1}) in
+        // column b; E~ itself is formed only where a probe needs it.
+        R P[C];
+        if constexpr (!kMatter) {
+            if constexpr (kEdge) {
+                compute_es(Di, Bi);
+                record(n);
+            }
+            if constexpr (!NEG) {
+                const R Bm1 = from_left(Bi[C - 1]);
+                const R Bm2 = from_left(Bi[C - 2]);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            R bsel;
-            if constexpr (!NEG)
-                bsel = (c >= 1) ? Bi[c >= 1 ? c - 1 : 0] : Bup;
-            else
-                bsel = Bi[c];
-            P[c] = fmad(bS, bsel, Es[c]);
+                for (int c = 0; c < C; ++c) {
+                    const R b1 = (c >= 1) ? Bi[c >= 1 ? c - 1 : 0] : Bm1;
+                    const R b2 = (c >= 2) ? Bi[c >= 2 ? c - 2 : 0] : (c == 1 ? Bm1 : Bm2);
+                    P[c] = fmad(Di[c], ce[c], fmad(k1, b1, k2 * b2));
+                }
+            } else {
+                const R Bp1 = from_right(Bi[0]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const R b2 = (c + 1 < C) ? Bi[c + 1 < C ? c + 1 : 0] : Bp1;
+                    P[c] = fmad(Di[c], ce[c], fmad(k1, Bi[c], k2 * b2));
+                }
+            }
+        } else {
+            compute_es(Di, Bi);
+            if constexpr (kEdge)
+                record(n);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                R bsel;
+                if constexpr (!NEG)
+                    bsel = (c >= 1) ? Bi[c >= 1 ? c - 1 : 0] : Bup;
+                else
+                    bsel = Bi[c];
+                P[c] = fmad(bS, bsel, Es[c]);
+            }
         }
         const R PR = from_right(P[0]);
 #pragma unroll
@@ -496,28 +525,26 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const R pn = (c + 1 < C) ? P[c + 1 < C ? c + 1 : 0] : PR;
             Bn[c] = Bi[c] + (P[c] - pn);
         }
-        // (10d) H~ = S H* with the Table 1 D average
-        const R DR = from_right(Di[0]);
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const R dn = (c + 1 < C) ? Di[c + 1 < C ? c + 1 : 0] : DR;
-            if constexpr (kMatter)
-                Hs[c] = fmad(Bn[c], ch[c], -(gh[c] * (dn + Di[c])));
-            else
-                Hs[c] = fmad(Bn[c], ch[c], -(hb * (dn + Di[c])));
-        }
-        // (10b) Ampere with the Table 1 dD/dz, telescoped:
+        // (10d) H~ = S H* with the Table 1 D average and (10b) Ampere with
+        // the Table 1 dD/dz, telescoped:
         //   X_k = H~_k + bS D_sel(k),  D' = D + (X_{k-1} - X_k),
-        // D_sel(k) = D_k (column a) or D_{k+1} (column b).
+        // D_sel(k) = D_k (column a) or D_{k+1} (column b); for a moving
+        // modulation X_k = cH B'_k + (bS - hb) D_1 - hb D_2 with
+        // (D_1, D_2) = (D_k, D_{k+1}) in column a, (D_{k+1}, D_k) in column b.
+        const R DR = from_right(Di[0]);
         R X[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            R dsel;
-            if constexpr (!NEG)
-                dsel = Di[c];
-            else
-                dsel = (c + 1 < C) ? Di[c + 1 < C ? c + 1 : 0] : DR;
-            X[c] = fmad(bS, dsel, Hs[c]);
+            const R dn = (c + 1 < C) ? Di[c + 1 < C ? c + 1 : 0] : DR;
+            if constexpr (!kMatter) {
+                if constexpr (!NEG)
+                    X[c] = fmad(Bn[c], ch[c], fmad(k1, Di[c], k2 * dn));
+                else
+                    X[c] = fmad(Bn[c], ch[c], fmad(k1, dn, k2 * Di[c]));
+            } else {
+                const R hs = fmad(Bn[c], ch[c], -(gh[c] * (dn + Di[c])));
+                X[c] = fmad(bS, NEG ? dn : Di[c], hs);
+            }
         }
         const R XL = from_left(X[C - 1]);
 #pragma unroll
