@@ -326,7 +326,8 @@ def main():
     plain = None
     if not args.no_plain:
         plain = {}
-        for name, maker in (("slab", lambda pr: W.slab_run(args.seed, precision=pr)),
+        for name, maker in (("interface", lambda pr: W.interface_run(args.seed, precision=pr)),
+                            ("slab", lambda pr: W.slab_run(args.seed, precision=pr)),
                             ("gradient", lambda pr: W.gradient_run(args.seed,
                                                                   precision=pr))):
             for pname, pr in (("f32", W.F32), ("f64", W.F64)):
@@ -427,6 +428,8 @@ def main():
         "batched_f64": batched_f64,
         "serving": serving,
         "plain": plain,
+        "batched_over_plain_slab": (value / plain[f"slab_{args.precision}"]["value"]
+                                    if plain else None),
         "tmm_sweep": tmm,
         "error": error,
         "cpu_baseline": cpu,

@@ -23,8 +23,10 @@
 // cE = S g mu', cH = S g eps' and hb is the per-cell S g beta / 2.  The
 // curl and velocity terms of (10a)/(10b) are telescoped into one
 // difference of per-cell sums (P = E~ + bS B_up, X = H~ + bS D_sel), which
-// keeps a uniform field exactly uniform and needs 12 floating-point
-// instructions per cell and step.
+// keeps a uniform field exactly uniform.  For a moving modulation E~ and
+// H~ are folded into P and X (one multiply and two fused multiply-adds
+// each): 10 floating-point instructions per cell and step (12 for moving
+// matter, whose hb varies per cell).
 //
 // The moving profile: at time tau*S the rest profile has moved by
 // m = rint(beta S tau) whole cells (FP64 on every path), so each lane keeps
