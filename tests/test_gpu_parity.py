@@ -249,3 +249,33 @@ def test_gradient_full_size_fp32_against_fp64(P):
     print(f"gradient 2^20 x 2^18: FP32 vs FP64 dft {e_dft:.2e} trace {e_tr:.2e}")
     assert a["status"] == 0 and b["status"] == 0
     assert e_dft < 1e-3 and e_tr < 1e-3
+
+
+def test_full_crystal_batch_in_benchmark_configuration(P):
+    """The whole 4096-run FP32 crystal batch at full step counts, in the
+    launch configuration the benchmark times (autotuned tiling): every run
+    finishes with finite probes, and the probe spectra of the three
+    smallest runs (4096+ cells, 16384+ steps each) match the oracle."""
+    import oracle as O
+    probs = W.crystal_runs(0, count=4096, precision=W.F32)
+    with P.Batch(probs, record_trace=False, fields=False) as b:
+        b.autotune(trial_blocks=4)
+        b.run()
+        got = b.collect()
+        st = b.stats()
+    assert all(g["status"] == 0 for g in got)
+    order = np.argsort([p.nz for p in probs])[:3]
+    for i in order:
+        want = O.solve(probs[i], fields=False)
+        e = rel(got[i]["dft"], want["dft"])
+        print(f"run {i} nz={probs[i].nz} steps={probs[i].steps} C={st['cells_per_lane']} "
+              f"T={st['block_steps']}: DFT rel err {e:.2e}", flush=True)
+        assert e < TOL32
+
+
+def test_slab_full_size_fp64(P):
+    """The 65536-cell moving slab for all 131072 steps (8.6e9 cell-updates)
+    in FP64 against the oracle."""
+    p = W.slab_run(0)
+    got = P.gfdtd_solve(p)
+    compare(got, oracle.solve(p), TOL64, "slab 65536x131072 f64")
