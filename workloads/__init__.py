@@ -9,10 +9,12 @@ Units are normalised throughout: c = eps0 = mu0 = 1, the cell size is 1 and
 time is measured in cell transit times, so the Courant number S is the time
 step and beta = v/c.
 
-The five workload families follow the structures the paper illustrates in
-its Fig. 1 (interface, slab, bilayer crystal, gradient) and validates in
-Section 6 (Figs. 5-8); sizes and distributions are the synthetic benchmark
-configurations stated in the design doc.
+The workload families follow the structures the paper illustrates in its
+Fig. 1 (interface, slab, bilayer crystal, gradient) and validates in
+Section 6 (Figs. 5-8), plus the plane waves on rings of the stability
+analysis (Section 5, Fig. 4) and multilayer stacks for the transfer-matrix
+method (App. B.3); each generator's docstring states its sizes and
+distributions.
 """
 from __future__ import annotations
 
