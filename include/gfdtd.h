@@ -138,7 +138,7 @@ typedef struct gfdtd_problem {
     int32_t nprobe;              /* 0..GFDTD_MAX_PROBES                    */
     int32_t nfreq;               /* >= 0                                   */
     int32_t reserved0;
-    int64_t nz;                  /* E nodes, >= 8                          */
+    int64_t nz;                  /* E nodes, 8 <= nz < 2^31 - 2^20         */
     double courant;              /* S = dt/dz, > 0                         */
     double beta;                 /* v/c, |beta| < 1 and |beta| S <= 0.9    */
     const double *eps_rest;      /* host, nz, > 0 and finite               */

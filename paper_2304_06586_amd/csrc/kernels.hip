@@ -266,6 +266,15 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     // wrapped on a ring); with a finite-duration modulation it holds the
     // background coefficient while the profile is switched off.
     R ce[C], ch[C], ge[C], gh[C];
+    // Window indices are clamped in 32 bits: nz < 2^31 - 2^20 is validated,
+    // and kb - m is saturated to a range whose ends clamp to the same grid
+    // cells, so base + c cannot overflow.
+    const int nz32 = (int)nz;
+    auto win_base = [&](int m) __attribute__((always_inline)) {
+        const int64_t b = kb - m;
+        constexpr int64_t lo = -(int64_t(1) << 30), hi = (int64_t(1) << 31) - 64;
+        return (int)(b < lo ? lo : (b > hi ? hi : b));
+    };
     auto load_e = [&](int m) __attribute__((always_inline)) {
         if constexpr (RING) {
             int64_t i = wrapi(kb - m, nz);
@@ -277,12 +286,23 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 i = ring_next(i, nz);
             }
         } else {
+            const int base = win_base(m);
+            if (x0 - m >= 0 && x0 - m + W <= nz) {
+                // the whole wave's window lies on the grid: no clamps
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int64_t i = clampi(kb + c - m, 0, nz - 1);
-                ce[c] = cEp[i];
-                if constexpr (kMatter)
-                    ge[c] = gBp[i];
+                for (int c = 0; c < C; ++c) {
+                    ce[c] = cEp[base + c];
+                    if constexpr (kMatter)
+                        ge[c] = gBp[base + c];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int i = min(max(base + c, 0), nz32 - 1);
+                    ce[c] = cEp[i];
+                    if constexpr (kMatter)
+                        ge[c] = gBp[i];
+                }
             }
         }
     };
@@ -297,12 +317,22 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 i = ring_next(i, nz);
             }
         } else {
+            const int base = win_base(m);
+            if (x0 - m >= 0 && x0 - m + W <= nz - 1) {
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const int64_t i = clampi(kb + c - m, 0, nz - 2);
-                ch[c] = cHp[i];
-                if constexpr (kMatter)
-                    gh[c] = gBp[i];
+                for (int c = 0; c < C; ++c) {
+                    ch[c] = cHp[base + c];
+                    if constexpr (kMatter)
+                        gh[c] = gBp[base + c];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int i = min(max(base + c, 0), nz32 - 2);
+                    ch[c] = cHp[i];
+                    if constexpr (kMatter)
+                        gh[c] = gBp[i];
+                }
             }
         }
     };

@@ -66,8 +66,9 @@ gfdtd_status validate(const gfdtd_problem *p, int64_t steps)
         return fail(GFDTD_E_INVALID, "unknown end condition %d", p->abc);
     if (p->nz < 8)
         return fail(GFDTD_E_INVALID, "nz = %lld < 8", (long long)p->nz);
-    if (p->nz > (int64_t(1) << 31))
-        return fail(GFDTD_E_INVALID, "nz = %lld too large", (long long)p->nz);
+    if (p->nz > (int64_t(1) << 31) - (int64_t(1) << 20))
+        return fail(GFDTD_E_INVALID, "nz = %lld too large (limit 2^31 - 2^20)",
+                    (long long)p->nz);
     if (steps < 0)
         return fail(GFDTD_E_INVALID, "steps = %lld < 0", (long long)steps);
     if (!finite_pos(p->courant))

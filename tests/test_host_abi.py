@@ -67,7 +67,7 @@ def _ok():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nz", 7), ("courant", 0.0), ("courant", float("nan")), ("beta", 1.0),
+    ("nz", 7), ("nz", 2**31 - 2**20 + 1), ("courant", 0.0), ("courant", float("nan")), ("beta", 1.0),
     ("beta", -1.5), ("src_cell", 0), ("src_cell", 199), ("kind", 5),
     ("precision", 3), ("abc", 9),
 ])
