@@ -209,6 +209,10 @@ gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
  * (0 = auto), block_steps = temporal block depth, steps per launch
  * (0 = auto; 1 for GFDTD_VARIANT_STEP), use_graph: -1 auto, 0 plain
  * launches, 1 capture the launch sequence in a hipGraph.
+ * tile_waves in 0..4 (0 = auto): waves that step one tile side by side,
+ * sharing overlap cells through LDS (rings always use 1);
+ * exchange_steps in 0..16 (0 = auto, 8): steps between the overlap
+ * refreshes of multi-wave tiles.
  * The result does not depend on these options (bit for bit).
  */
 typedef struct gfdtd_exec {
@@ -217,6 +221,8 @@ typedef struct gfdtd_exec {
     int32_t cells_per_lane;
     int32_t block_steps;
     int32_t use_graph;
+    int32_t tile_waves;
+    int32_t exchange_steps;
     int32_t reserved0;
 } gfdtd_exec;
 
@@ -271,6 +277,8 @@ typedef struct gfdtd_stats {
     double step_ms;              /* device time of the last pass's stepping
                                     launches (HIP events on the stream)    */
     double pass_ms;              /* device time of the whole last pass     */
+    int32_t tile_waves;          /* waves per tile                         */
+    int32_t exchange_steps;      /* steps between overlap refreshes        */
 } gfdtd_stats;
 
 gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
@@ -278,7 +286,8 @@ gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
 /*
  * Autotuner: for each (precision, kind) group of the batch, time
  * trial_blocks launches (0 = 4) of every valid (cells per lane in {4, 8,
- * 16}, steps per launch in {8, 16, 24, 32, 48, 64}) on the prepared runs
+ * 12, 16}, steps per launch in {8, 16, 24, 32, 48, 64}, 1 or 4 waves per
+ * tile off rings) on the prepared runs
  * and keep the fastest per cell-update; results of a pass do not depend on
  * the choice.  Choices are cached in the process by precision, kind, sign
  * mix and the size scales of the group.  Writes the first group's choice to

@@ -12,6 +12,11 @@ namespace gfdtd {
 
 constexpr int kWave = 64;            // CDNA wavefront width
 constexpr int kWavesPerGroup = 4;    // independent wave tiles per workgroup
+constexpr int kMaxTileWaves = 4;     // waves of one multi-wave tile (<= 4)
+constexpr int kXSlot = 64;           // cells per overlap slot (>= xl C, xr C)
+constexpr int kXCoefFields = 6;      // D, B and up to 4 coefficient windows
+// LDS per wave and buffer: one slot of D, B, one of D, B and the windows
+constexpr int kXStride = (2 + kXCoefFields) * kXSlot;
 constexpr int64_t kPad = 2048;       // cells of padding before and after
                                      // every field array (>= 64 * C)
 
@@ -24,7 +29,7 @@ struct RunDesc {
     int64_t start_block;   // global block index at which step 1 runs
     int64_t nsrc;          // source samples for steps 1..nsrc
     int64_t src_cell;
-    int64_t own_cells;     // cells each tile of this run stores
+    int64_t own_cells;     // cells each tile of this run stores (all waves)
     double S;              // Courant number
     double beta;
     double bS;             // beta * S (one rounding; also the shift rate)
@@ -35,6 +40,10 @@ struct RunDesc {
     int32_t nprobe;
     int32_t abc;           // GFDTD_ABC_* (GFDTD_ABC_PERIODIC: a ring)
     int32_t windowed;      // finite-duration modulation (t_on, t_off)
+    int32_t xl, xr;        // multi-wave tiles: overlap lanes refreshed from
+                           // the left / right neighbour wave
+    int32_t xk;            // steps between refreshes (>= 1)
+    int32_t pad0;
     void *D[2];            // ping-pong D (run precision)
     void *B[2];            // ping-pong B
     const void *cE;        // E-node coefficient: S/eps' or S g mu'
@@ -100,8 +109,9 @@ hipError_t launch_init(const PrepDesc *dev_descs, int count, int64_t max_nz,
                        int precision, hipStream_t stream);
 // Steps the first ntiles tiles by one block.  win selects the kernel for
 // runs with a finite-duration modulation; each kernel skips the other's
-// runs, so a group holding both is stepped by two launches.
-hipError_t launch_tiles(int precision, int kind, bool ring, bool win, int C,
+// runs, so a group holding both is stepped by two launches.  G = waves per
+// tile (1..kMaxTileWaves); every run of the launch is tiled with that G.
+hipError_t launch_tiles(int precision, int kind, bool ring, bool win, int C, int G,
                         const RunDesc *runs, const TileRef *tiles, int64_t block,
                         int T, int ntiles, hipStream_t stream);
 

@@ -202,10 +202,23 @@ __device__ __forceinline__ R pick(const R (&a)[C], int idx)
 
 // ------------------------------------------------------------- the tile
 
-template <typename R, int C, int KIND, bool NEG, bool RING, bool WIN>
-__device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
-                                          int tile, int64_t block, int T)
+// Workgroup barrier of a multi-wave tile.  A wave takes part only while
+// it has active lanes: where the compiler lays out a wave-uniform branch
+// as lane-masked code, the side a wave does not take runs with an empty
+// mask and must not count as a barrier.  On the side it takes, all 64
+// lanes are active at every barrier.
+__device__ __forceinline__ void tile_barrier()
 {
+    if (__builtin_amdgcn_read_exec() != 0ull)
+        __syncthreads();
+}
+
+template <typename R, int C, int KIND, bool NEG, bool RING, bool WIN, bool MW>
+__device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
+                                          int tile, int w, int G_, int64_t block, int T,
+                                          R *__restrict__ xbuf)
+{
+    const int G = MW ? G_ : 1;          // one-wave tiles carry no refresh code
     constexpr bool kMatter = (KIND == GFDTD_MATTER);
     const int lane = threadIdx.x & (kWave - 1);
 
@@ -233,8 +246,33 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     const int abc = rd->abc;
     const int nprobe = rd->nprobe;
     const int64_t W = (int64_t)kWave * C;
-    const int64_t x0 = (int64_t)tile * rd->own_cells - (int64_t)hl * C;
+    // A tile is G waves side by side (wave w of the tile here).  Adjacent
+    // waves share ov = xl + xr lanes: every xk steps each refreshes its
+    // outer xl (left) and xr (right) lanes from its neighbours, which hold
+    // them inside their own valid region.  The tile's outer ends carry the
+    // halos hl and hr of the whole T-step block.
+    const int xl = G > 1 ? rd->xl : 0;
+    const int xr = G > 1 ? rd->xr : 0;
+    const int xk = rd->xk;
+    const int ov = xl + xr;
+    const int64_t x0 = (int64_t)tile * rd->own_cells - (int64_t)hl * C +
+                       (int64_t)w * (kWave - ov) * C;
     const int64_t kb = x0 + (int64_t)lane * C;
+    if (MW && G > 1 && !RING && x0 >= nz) {
+        // entirely past the grid end: nothing to step, but the tile's
+        // waves meet at every refresh; the left neighbour reads zeros
+        const int nx = (nsub - 1) / xk;
+        for (int e = 0; e < nx; ++e) {
+            R *p = xbuf + ((e & 1) * kMaxTileWaves + w) * kXStride +
+                   (NEG ? 2 * kXSlot : kXCoefFields * kXSlot);
+            for (int i = lane; i < (NEG ? kXCoefFields : 2) * kXSlot; i += kWave)
+                p[i] = (R)0;
+            tile_barrier();
+        }
+        return;
+    }
+    const int own_l = w == 0 ? hl : xl;             // owned lanes [own_l, own_r)
+    const int own_r = w == G - 1 ? kWave - hr : kWave - xr;
 
     const R *__restrict__ Dsrc = static_cast<const R *>(rd->D[par]);
     const R *__restrict__ Bsrc = static_cast<const R *>(rd->B[par]);
@@ -421,8 +459,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             cs = (int)((ks - x0) % C);
         }
     }
-    const int64_t own_lo = x0 + (int64_t)hl * C;
-    const int64_t own_hi = x0 + W - (int64_t)hr * C;
+    const int64_t own_lo = x0 + (int64_t)own_l * C;
+    const int64_t own_hi = x0 + (int64_t)own_r * C;
 
     R Es[C], sums[C];
     R D2[C], B2[C];   // second register set of the ping-pong step pair
@@ -637,6 +675,65 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             ghosts(Bn);
     };
 
+    // Overlap refresh of a multi-wave tile through LDS.  Per wave and
+    // buffer: slot R = the lanes [64-ov, 64-xr) the right neighbour holds
+    // as its left overlap, slot L = the lanes [xl, ov) the left neighbour
+    // holds as its right overlap; D and B, and on the side where window
+    // shifts bring in a cell from the neighbouring lane (the left for
+    // column a, the right for column b) also the coefficient windows,
+    // whose new edge cell is only valid inside the halo.  Two buffers
+    // alternate, so one barrier per refresh suffices: a wave rewrites a
+    // buffer only after the next barrier, which every wave reaches after
+    // its reads of that buffer.
+    int nxch = 0;
+    constexpr int offL = NEG ? 2 * kXSlot : kXCoefFields * kXSlot;
+    auto put = [&](R *p, auto coef_tag) __attribute__((always_inline)) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            p[c] = D[c];
+            p[kXSlot + c] = B[c];
+            if constexpr (decltype(coef_tag)::value) {
+                p[2 * kXSlot + c] = ce[c];
+                p[3 * kXSlot + c] = ch[c];
+                if constexpr (kMatter) {
+                    p[4 * kXSlot + c] = ge[c];
+                    p[5 * kXSlot + c] = gh[c];
+                }
+            }
+        }
+    };
+    auto get = [&](const R *p, auto coef_tag) __attribute__((always_inline)) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            D[c] = p[c];
+            B[c] = p[kXSlot + c];
+            if constexpr (decltype(coef_tag)::value) {
+                ce[c] = p[2 * kXSlot + c];
+                ch[c] = p[3 * kXSlot + c];
+                if constexpr (kMatter) {
+                    ge[c] = p[4 * kXSlot + c];
+                    gh[c] = p[5 * kXSlot + c];
+                }
+            }
+        }
+    };
+    using CoefR = std::integral_constant<bool, !NEG>;   // slot R carries windows
+    using CoefL = std::integral_constant<bool, NEG>;    // slot L carries windows
+    auto exchange = [&]() __attribute__((always_inline)) {
+        // every address is lane * C plus a wave-uniform offset
+        R *lp = xbuf + lane * C + ((nxch & 1) * kMaxTileWaves + w) * kXStride;
+        if (w + 1 < G && lane >= kWave - ov && lane < kWave - xr)
+            put(lp - (kWave - ov) * C, CoefR{});
+        if (w > 0 && lane >= xl && lane < ov)
+            put(lp + offL - xl * C, CoefL{});
+        tile_barrier();
+        if (w > 0 && lane < xl)
+            get(lp - kXStride, CoefR{});
+        if (w + 1 < G && lane >= kWave - xr)
+            get(lp + kXStride + offL - (kWave - xr) * C, CoefL{});
+        ++nxch;
+    };
+
     // The step loop.  The shift schedule of 64 steps at a time is computed
     // in FP64 by the per-node rule m = rint(beta S tau), one step per lane,
     // and kept as wave-wide bit masks: bit j of hmask = the H window moves
@@ -649,6 +746,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         constexpr bool kEdge = decltype(edge_tag)::value;
         int mEc = mE;                       // E shift at the current n - 1/2
         int mHc = mH;                       // H shift at the current n
+        int nextx = G > 1 ? xk : nsub;      // step count of the next refresh
         for (int s0 = 0; s0 < nsub; s0 += kWave) {
             const int len = nsub - s0 < kWave ? nsub - s0 : kWave;
             const int sl = s0 + lane;
@@ -671,8 +769,11 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 hsw = __ballot(sl > 0 && sl < nsub && aH != active(tn - 1.0));
                 esw = __ballot(sl < nsub && aE != active(tn - 0.5));
             }
-            // a move or switch after step j
-            const uint64_t bmask = emask | (hmask >> 1) | esw | (hsw >> 1);
+            // a move, switch or overlap refresh (every xk steps of a
+            // multi-wave tile, not after the last) after step j
+            const uint64_t bmask =
+                emask | (hmask >> 1) | esw | (hsw >> 1) |
+                (G > 1 ? __ballot(sl + 1 < nsub && (sl + 1) % xk == 0) : 0ull);
             auto update_h = [&](int q) __attribute__((always_inline)) {
                 if ((hmask >> q) & 1ull) {
                     shift_h();
@@ -714,6 +815,10 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                         B[c] = B2[c];
                     }
                 }
+                if (MW && s0 + stop + 1 == nextx && nextx < nsub) {
+                    exchange();
+                    nextx += xk;
+                }
                 if ((emask >> stop) & 1ull) {
                     shift_e();
                     mEc += dir;
@@ -742,19 +847,34 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     else
         steps_loop(std::false_type{});
 
-    if (lane >= hl && lane < kWave - hr) {
+    if (lane >= own_l && lane < own_r) {
         store_cells<R, C>(Ddst + kb, D);
         store_cells<R, C>(Bdst + kb, B);
     }
 }
 
-template <typename R, int C, int KIND, bool RING, bool WIN>
-__global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
-    const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
-    int64_t block, int T, int ntiles)
+// Occupancy target: the refresh code of a multi-wave FP32 tile of a moving
+// modulation at 12 cells per lane would otherwise just exceed the 96
+// registers of 5 waves per SIMD.
+template <typename R, int C, int KIND, bool MW>
+constexpr int mw_waves()
 {
+    return (MW && sizeof(R) == 4 && C == 12 && KIND == GFDTD_MODULATION) ? 5 : 1;
+}
+
+// MW = false: four independent one-wave tiles per workgroup (G = 1).
+// MW = true: one tile of G waves per workgroup (blockDim = 64 G).
+template <typename R, int C, int KIND, bool RING, bool WIN, bool MW>
+__global__ __launch_bounds__(kWave *kWavesPerGroup)
+__attribute__((amdgpu_waves_per_eu(mw_waves<R, C, KIND, MW>()))) void k_tiles(
+    const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
+    int64_t block, int T, int ntiles, int G)
+{
+    __shared__ __align__(16) R xbuf[MW ? 2 * kMaxTileWaves * kXStride : 1];
+    const int wv = (int)(threadIdx.x / kWave);
     const int t = __builtin_amdgcn_readfirstlane(
-        (int)(blockIdx.x * kWavesPerGroup + (threadIdx.x / kWave)));
+        MW ? (int)blockIdx.x : (int)(blockIdx.x * kWavesPerGroup) + wv);
+    const int w = __builtin_amdgcn_readfirstlane(MW ? wv : 0);
     if (t >= ntiles)
         return;
     const TileRef ref = tiles[t];
@@ -765,36 +885,34 @@ __global__ __launch_bounds__(kWave *kWavesPerGroup) void k_tiles(
     if ((KIND != GFDTD_MATTER && rd->windowed != 0) != WIN)
         return;
     if (rd->neg)
-        tile_body<R, C, KIND, true, RING, WIN>(rd, ref.tile, block, T);
+        tile_body<R, C, KIND, true, RING, WIN, MW>(rd, ref.tile, w, G, block, T, xbuf);
     else
-        tile_body<R, C, KIND, false, RING, WIN>(rd, ref.tile, block, T);
+        tile_body<R, C, KIND, false, RING, WIN, MW>(rd, ref.tile, w, G, block, T, xbuf);
 }
 
-template <typename R, int KIND, bool RING, bool WIN>
-static hipError_t launch_tiles_c(int C, const RunDesc *runs,
+template <typename R, int KIND, bool RING, bool WIN, bool MW>
+static hipError_t launch_tiles_g(int C, int G, const RunDesc *runs,
                                  const TileRef *tiles, int64_t block, int T,
                                  int ntiles, hipStream_t stream)
 {
-    if (ntiles <= 0)
-        return hipSuccess;
-    const dim3 grid((ntiles + kWavesPerGroup - 1) / kWavesPerGroup);
-    const dim3 blk(kWave * kWavesPerGroup);
+    const dim3 grid(MW ? ntiles : (ntiles + kWavesPerGroup - 1) / kWavesPerGroup);
+    const dim3 blk(kWave * (MW ? G : kWavesPerGroup));
     switch (C) {
     case 4:
-        hipLaunchKernelGGL((k_tiles<R, 4, KIND, RING, WIN>), grid, blk, 0, stream, runs,
-                           tiles, block, T, ntiles);
+        hipLaunchKernelGGL((k_tiles<R, 4, KIND, RING, WIN, MW>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles, G);
         break;
     case 8:
-        hipLaunchKernelGGL((k_tiles<R, 8, KIND, RING, WIN>), grid, blk, 0, stream, runs,
-                           tiles, block, T, ntiles);
+        hipLaunchKernelGGL((k_tiles<R, 8, KIND, RING, WIN, MW>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles, G);
         break;
     case 12:
-        hipLaunchKernelGGL((k_tiles<R, 12, KIND, RING, WIN>), grid, blk, 0, stream, runs,
-                           tiles, block, T, ntiles);
+        hipLaunchKernelGGL((k_tiles<R, 12, KIND, RING, WIN, MW>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles, G);
         break;
     case 16:
-        hipLaunchKernelGGL((k_tiles<R, 16, KIND, RING, WIN>), grid, blk, 0, stream, runs,
-                           tiles, block, T, ntiles);
+        hipLaunchKernelGGL((k_tiles<R, 16, KIND, RING, WIN, MW>), grid, blk, 0, stream, runs,
+                           tiles, block, T, ntiles, G);
         break;
     default:
         return hipErrorInvalidValue;
@@ -802,31 +920,50 @@ static hipError_t launch_tiles_c(int C, const RunDesc *runs,
     return hipGetLastError();
 }
 
+// Multi-wave tiles only off rings.
+template <typename R, int KIND, bool RING, bool WIN>
+static hipError_t launch_tiles_c(int C, int G, const RunDesc *runs,
+                                 const TileRef *tiles, int64_t block, int T,
+                                 int ntiles, hipStream_t stream)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    if (G < 1 || G > kMaxTileWaves || (RING && G > 1))
+        return hipErrorInvalidValue;
+    if constexpr (!RING) {
+        if (G > 1)
+            return launch_tiles_g<R, KIND, RING, WIN, true>(C, G, runs, tiles, block, T,
+                                                            ntiles, stream);
+    }
+    return launch_tiles_g<R, KIND, RING, WIN, false>(C, G, runs, tiles, block, T, ntiles,
+                                                     stream);
+}
+
 template <typename R>
-static hipError_t launch_tiles_r(int kind, bool ring, bool win, int C,
+static hipError_t launch_tiles_r(int kind, bool ring, bool win, int C, int G,
                                  const RunDesc *runs, const TileRef *tiles,
                                  int64_t block, int T, int ntiles, hipStream_t stream)
 {
     if (kind == GFDTD_MATTER) {        // moving matter has no time window
         if (win)
             return hipSuccess;
-        return ring ? launch_tiles_c<R, GFDTD_MATTER, true, false>(C, runs, tiles, block, T, ntiles, stream)
-                    : launch_tiles_c<R, GFDTD_MATTER, false, false>(C, runs, tiles, block, T, ntiles, stream);
+        return ring ? launch_tiles_c<R, GFDTD_MATTER, true, false>(C, G, runs, tiles, block, T, ntiles, stream)
+                    : launch_tiles_c<R, GFDTD_MATTER, false, false>(C, G, runs, tiles, block, T, ntiles, stream);
     }
     if (win)
-        return ring ? launch_tiles_c<R, GFDTD_MODULATION, true, true>(C, runs, tiles, block, T, ntiles, stream)
-                    : launch_tiles_c<R, GFDTD_MODULATION, false, true>(C, runs, tiles, block, T, ntiles, stream);
-    return ring ? launch_tiles_c<R, GFDTD_MODULATION, true, false>(C, runs, tiles, block, T, ntiles, stream)
-                : launch_tiles_c<R, GFDTD_MODULATION, false, false>(C, runs, tiles, block, T, ntiles, stream);
+        return ring ? launch_tiles_c<R, GFDTD_MODULATION, true, true>(C, G, runs, tiles, block, T, ntiles, stream)
+                    : launch_tiles_c<R, GFDTD_MODULATION, false, true>(C, G, runs, tiles, block, T, ntiles, stream);
+    return ring ? launch_tiles_c<R, GFDTD_MODULATION, true, false>(C, G, runs, tiles, block, T, ntiles, stream)
+                : launch_tiles_c<R, GFDTD_MODULATION, false, false>(C, G, runs, tiles, block, T, ntiles, stream);
 }
 
-hipError_t launch_tiles(int precision, int kind, bool ring, bool win, int C,
+hipError_t launch_tiles(int precision, int kind, bool ring, bool win, int C, int G,
                         const RunDesc *runs, const TileRef *tiles, int64_t block,
                         int T, int ntiles, hipStream_t stream)
 {
     if (precision == GFDTD_F32)
-        return launch_tiles_r<float>(kind, ring, win, C, runs, tiles, block, T, ntiles, stream);
-    return launch_tiles_r<double>(kind, ring, win, C, runs, tiles, block, T, ntiles, stream);
+        return launch_tiles_r<float>(kind, ring, win, C, G, runs, tiles, block, T, ntiles, stream);
+    return launch_tiles_r<double>(kind, ring, win, C, G, runs, tiles, block, T, ntiles, stream);
 }
 
 // ------------------------------------------------------------- set-up

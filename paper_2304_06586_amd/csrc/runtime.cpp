@@ -352,7 +352,7 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 // per lane and 24 steps when the group holds few cells (more, narrower
 // tiles keep more SIMDs busy).
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
-                   int64_t total_cells, int &C, int &T)
+                   int64_t total_cells, bool ring, int &C, int &T, int &G, int &K)
 {
     const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
     const bool small = total_cells < (int64_t)4 << 20;
@@ -366,6 +366,10 @@ void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
         T = small ? 24 : 32;
     if (max_steps > 0 && T > max_steps)
         T = (int)std::max<int64_t>(1, max_steps);
+    G = (ex && ex->tile_waves > 0) ? ex->tile_waves : 1;
+    if (ring || variant == GFDTD_VARIANT_STEP)
+        G = 1;                           // rings and single steps: one-wave tiles
+    K = (ex && ex->exchange_steps > 0) ? ex->exchange_steps : 8;
 }
 
 bool halo_lanes(double beta, int C, int T, int &hl, int &hr)
@@ -379,6 +383,34 @@ bool halo_lanes(double beta, int C, int T, int &hl, int &hr)
         hr = two;
     }
     return hl + hr < kWave;
+}
+
+bool tile_geometry(double beta, int C, int T, int G, int K, TileGeom &g)
+{
+    g = TileGeom{};
+    if (!halo_lanes(beta, C, T, g.hl, g.hr))
+        return false;
+    if (G <= 1) {
+        g.own = (int64_t)(kWave - g.hl - g.hr) * C;
+        return true;
+    }
+    if (G > kMaxTileWaves || K < 1)
+        return false;
+    // overlaps: the reach of K steps on each side, as the halos of a block
+    int xl, xr;
+    halo_lanes(beta, C, K, xl, xr);
+    const int ov = xl + xr;
+    // the lanes a wave hands over must stay valid between refreshes: clear
+    // of the outer halos and of the wave's own far overlap
+    if (xl * C > kXSlot || xr * C > kXSlot || g.hl + ov > kWave || g.hr + ov > kWave ||
+        ov + std::max(xl, xr) > kWave)
+        return false;
+    g.G = G;
+    g.xl = xl;
+    g.xr = xr;
+    g.xk = K;
+    g.own = ((int64_t)kWave * G - (int64_t)(G - 1) * ov - g.hl - g.hr) * C;
+    return true;
 }
 
 // ------------------------------------------------------------------- batch
@@ -399,6 +431,10 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         return fail(GFDTD_E_INVALID, "cells_per_lane must be 4, 8, 12 or 16");
     if (ex && (ex->block_steps < 0 || ex->block_steps > 256))
         return fail(GFDTD_E_INVALID, "block_steps outside 0..256");
+    if (ex && (ex->tile_waves < 0 || ex->tile_waves > kMaxTileWaves))
+        return fail(GFDTD_E_INVALID, "tile_waves outside 0..%d", kMaxTileWaves);
+    if (ex && (ex->exchange_steps < 0 || ex->exchange_steps > 16))
+        return fail(GFDTD_E_INVALID, "exchange_steps outside 0..16");
     runs.resize(count);
     for (int i = 0; i < count; ++i) {
         gfdtd_status st = validate(&probs[i], steps_in[i]);
@@ -428,7 +464,7 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
             }
         if (G.members.empty())
             continue;
-        choose_tiling(G.precision, ex, max_steps, cells, G.C, G.T);
+        choose_tiling(G.precision, ex, max_steps, cells, G.ring, G.C, G.T, G.Gw, G.K);
         for (int i : G.members)
             runs[i].T = G.T;
         int64_t maxt = 0;
@@ -464,7 +500,9 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         for (int m = 0; m < nr; ++m) {
             RunHost &r = runs[G.members[m]];
             RunDesc rd;
-            fill_desc(r, G, 1, 1, kWave - 2, 0, rd, G.host_pd[m], G.host_dd[m]);
+            TileGeom g0;
+            g0.own = kWave - 2;
+            fill_desc(r, G, g0, 0, rd, G.host_pd[m], G.host_dd[m]);
             G.max_cells = std::max<int64_t>(G.max_cells, std::max(r.p.nz, r.L.nsrc));
             if (r.L.has_init_d || r.L.has_init_b)
                 G.max_init = std::max<int64_t>(G.max_init, r.p.nz);
@@ -528,15 +566,17 @@ gfdtd_status Batch::build_tiles(Group &G)
     for (int m = 0; m < nr; ++m) {
         RunHost &r = runs[G.members[m]];
         r.T = G.T;
-        int hl, hr;
-        if (!halo_lanes(r.p.beta, G.C, G.T, hl, hr))
-            return fail(GFDTD_E_INVALID, "block of %d steps too deep for %d cells per lane",
-                        G.T, G.C);
-        const int64_t own = (int64_t)(kWave - hl - hr) * G.C;
+        TileGeom g;
+        if (!tile_geometry(r.p.beta, G.C, G.T, G.Gw, G.K, g))
+            return fail(GFDTD_E_INVALID,
+                        "block of %d steps too deep for %d cells per lane "
+                        "(%d-wave tiles, refresh every %d steps)",
+                        G.T, G.C, G.Gw, G.K);
+        const int64_t own = g.own;
         const int64_t nt = (r.p.nz + own - 1) / own;
         PrepDesc pd;
         DftDesc dd;
-        fill_desc(r, G, hl, hr, own, 0, G.host_rd[m], pd, dd);
+        fill_desc(r, G, g, 0, G.host_rd[m], pd, dd);
         for (int64_t t = 0; t < nt; ++t)
             G.host_tiles.push_back(TileRef{m, (int32_t)t});
         G.tiles_prefix[m + 1] = G.tiles_prefix[m] + nt;
@@ -565,7 +605,10 @@ struct TuneKey {
                std::tie(o.group, o.neg, o.runs_log2, o.cells_log2, o.steps_log2);
     }
 };
-std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+struct TuneChoice {
+    int C, T, G;
+};
+std::map<TuneKey, TuneChoice> g_tune_cache;
 std::mutex g_tune_mutex;
 
 int ilog2(double x) { return x < 1.0 ? 0 : (int)std::floor(std::log2(x)); }
@@ -598,30 +641,36 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
             std::lock_guard<std::mutex> lk(g_tune_mutex);
             auto it = g_tune_cache.find(key);
             if (it != g_tune_cache.end()) {
-                G.C = it->second.first;
-                G.T = it->second.second;
+                G.C = it->second.C;
+                G.T = it->second.T;
+                G.Gw = it->second.G;
                 if ((st = build_tiles(G)) != GFDTD_OK)
                     return st;
                 continue;
             }
         }
-        const int defC = G.C, defT = G.T;
-        int bestC = G.C, bestT = G.T;
+        const int defC = G.C, defT = G.T, defG = G.Gw;
+        int bestC = G.C, bestT = G.T, bestG = G.Gw;
         double best = 1e300, def_time = 1e300;
         const int Cs[] = {4, 8, 12, 16};
         const int Ts[] = {8, 16, 24, 32, 48, 64};
+        const int nG = G.ring ? 1 : 2;
+        const int Gs[] = {1, kMaxTileWaves};
+        for (int gi = 0; gi < nG; ++gi)
         for (int C : Cs)
             for (int T : Ts) {
+                const int Gw = Gs[gi];
                 if ((double)T > steps && T != 8)
                     continue;
                 bool ok = true;
-                int hl, hr;
+                TileGeom tg;
                 for (int i : G.members)
-                    ok = ok && halo_lanes(runs[i].p.beta, C, T, hl, hr);
+                    ok = ok && tile_geometry(runs[i].p.beta, C, T, Gw, G.K, tg);
                 if (!ok)
                     continue;
                 G.C = C;
                 G.T = T;
+                G.Gw = Gw;
                 if ((st = build_tiles(G)) != GFDTD_OK)
                     return st;
                 const int64_t nb = std::min<int64_t>(trial + 1, G.nblocks);
@@ -637,7 +686,7 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                 auto launch = [&](int64_t b) {
                     hipError_t le = hipSuccess;
                     for (int w = 0; w < (G.has_window ? 2 : 1) && !le; ++w)
-                        le = launch_tiles(G.precision, G.kind, G.ring, w == 1, C,
+                        le = launch_tiles(G.precision, G.kind, G.ring, w == 1, C, Gw,
                                           reinterpret_cast<const RunDesc *>(ws + G.runs_off),
                                           reinterpret_cast<const TileRef *>(ws + G.tiles_off),
                                           b, T, live_tiles(G, b), stream);
@@ -656,12 +705,13 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                     (e = hipEventElapsedTime(&ms, t0, t1)))
                     return hip_fail(e, "autotune timing");
                 const double per = upd > 0.0 ? ms / upd : (double)ms;
-                if (C == defC && T == defT)
+                if (C == defC && T == defT && Gw == defG)
                     def_time = per;
                 if (per < best) {
                     best = per;
                     bestC = C;
                     bestT = T;
+                    bestG = Gw;
                 }
             }
         // keep the default unless a candidate is clearly faster (trial
@@ -669,13 +719,15 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
         if (def_time < 1e300 && best > def_time / 1.03) {
             bestC = defC;
             bestT = defT;
+            bestG = defG;
         }
         G.C = bestC;
         G.T = bestT;
+        G.Gw = bestG;
         if ((st = build_tiles(G)) != GFDTD_OK)
             return st;
         std::lock_guard<std::mutex> lk(g_tune_mutex);
-        g_tune_cache[key] = {bestC, bestT};
+        g_tune_cache[key] = {bestC, bestT, bestG};
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
@@ -699,20 +751,21 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
         chosen->variant = GFDTD_VARIANT_TILED;
         chosen->cells_per_lane = groups[0].C;
         chosen->block_steps = groups[0].T;
+        chosen->tile_waves = groups[0].Gw;
+        chosen->exchange_steps = groups[0].K;
         chosen->use_graph = graph_on ? 1 : 0;
     }
     return GFDTD_OK;
 }
 
-void Batch::fill_desc(RunHost &r, const Group &G, int hl, int hr, int64_t own,
-                      int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd)
+void Batch::fill_desc(RunHost &r, const Group &G, const TileGeom &g, int64_t start_block,
+                      RunDesc &rd, PrepDesc &pd, DftDesc &dd)
 {
-    fill_run_desc(ws, r, G.precision, hl, hr, own, start_block, rd, pd, dd);
+    fill_run_desc(ws, r, G.precision, g, start_block, rd, pd, dd);
 }
 
-void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
-                   int64_t own, int64_t start_block, RunDesc &rd, PrepDesc &pd,
-                   DftDesc &dd)
+void fill_run_desc(char *base, const RunHost &r, int precision, const TileGeom &g,
+                   int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd)
 {
     const size_t w = precision == GFDTD_F32 ? 4 : 8;
     const gfdtd_problem &p = r.p;
@@ -722,14 +775,17 @@ void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
     rd.start_block = start_block;
     rd.nsrc = r.L.nsrc;
     rd.src_cell = p.src_cell;
-    rd.own_cells = own;
+    rd.own_cells = g.own;
     rd.S = p.courant;
     rd.beta = p.beta;
     rd.bS = p.beta * p.courant;
     rd.hb = 0.5 * p.beta * p.courant;
     rd.neg = p.beta < 0.0;
-    rd.hl = hl;
-    rd.hr = hr;
+    rd.hl = g.hl;
+    rd.hr = g.hr;
+    rd.xl = g.xl;
+    rd.xr = g.xr;
+    rd.xk = g.xk;
     rd.nprobe = p.nprobe;
     rd.abc = p.abc;
     rd.windowed = (p.flags & GFDTD_FLAG_TIME_WINDOW) ? 1 : 0;
@@ -839,7 +895,7 @@ gfdtd_status Batch::enqueue_steps(hipStream_t s)
             if (b >= G.nblocks)
                 continue;
             for (int w = 0; w < (G.has_window ? 2 : 1); ++w) {
-                hipError_t e = launch_tiles(G.precision, G.kind, G.ring, w == 1, G.C,
+                hipError_t e = launch_tiles(G.precision, G.kind, G.ring, w == 1, G.C, G.Gw,
                                             reinterpret_cast<const RunDesc *>(ws + G.runs_off),
                                             reinterpret_cast<const TileRef *>(ws + G.tiles_off),
                                             b, G.T, live_tiles(G, b), s);
@@ -1027,6 +1083,8 @@ void Batch::stats(gfdtd_stats *s) const
 {
     s->cells_per_lane = groups.empty() ? 0 : groups[0].C;
     s->block_steps = groups.empty() ? 0 : groups[0].T;
+    s->tile_waves = groups.empty() ? 0 : groups[0].Gw;
+    s->exchange_steps = groups.empty() ? 0 : groups[0].K;
     s->graph = graph_on ? 1 : 0;
     s->launches = launches;
     s->tiles = tiles_total;

@@ -42,8 +42,17 @@ void carve_run(Carver &cv, const gfdtd_problem *p, int64_t steps, RunLayout &L);
 size_t table_bytes(int nruns, int64_t max_tiles);
 int64_t max_tiles_of(int64_t nz);
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
-                   int64_t total_cells, int &C, int &T);
+                   int64_t total_cells, bool ring, int &C, int &T, int &G, int &K);
 bool halo_lanes(double beta, int C, int T, int &hl, int &hr);
+
+// Lane geometry of the tiles of one run: outer halos hl, hr for a T-step
+// block; for G-wave tiles the overlaps xl, xr refreshed every K steps;
+// own = cells a tile stores.
+struct TileGeom {
+    int G = 1, hl = 1, hr = 1, xl = 0, xr = 0, xk = 1;
+    int64_t own = 0;
+};
+bool tile_geometry(double beta, int C, int T, int G, int K, TileGeom &g);
 
 // A run with host copies of its inputs.
 struct RunHost {
@@ -61,9 +70,8 @@ RunHost make_run_host(const gfdtd_problem &p, int64_t steps);
 // frequencies, initial fields) into the workspace at base.
 hipError_t upload_run_inputs(char *base, const RunHost &r, hipStream_t stream);
 
-void fill_run_desc(char *base, const RunHost &r, int precision, int hl, int hr,
-                   int64_t own, int64_t start_block, RunDesc &rd, PrepDesc &pd,
-                   DftDesc &dd);
+void fill_run_desc(char *base, const RunHost &r, int precision, const TileGeom &g,
+                   int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd);
 
 // The state a run of zero steps returns: its initial fields (or zeros),
 // rounded to the run precision; either pointer may be null.
@@ -75,6 +83,7 @@ gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *
 // Runs of one precision and kind, stepped by one kernel instantiation.
 struct Group {
     int precision = 0, kind = 0, C = 16, T = 16;
+    int Gw = 1, K = 8;                // waves per tile, steps per refresh
     bool ring = false;                // periodic ends
     bool has_window = false;          // holds finite-duration modulations
     std::vector<int> members;         // run indices, longest first
@@ -109,8 +118,8 @@ struct Batch {
     gfdtd_status prepare(const gfdtd_problem *probs, const int64_t *steps,
                          int32_t count, const gfdtd_exec *ex, void *ws,
                          size_t ws_bytes, hipStream_t stream);
-    void fill_desc(RunHost &r, const Group &G, int hl, int hr, int64_t own,
-                   int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd);
+    void fill_desc(RunHost &r, const Group &G, const TileGeom &g, int64_t start_block,
+                   RunDesc &rd, PrepDesc &pd, DftDesc &dd);
     int live_tiles(const Group &G, int64_t b) const;
     bool auto_graph() const;
     gfdtd_status enqueue_zero(hipStream_t s);

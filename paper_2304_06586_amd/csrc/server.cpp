@@ -159,8 +159,8 @@ struct Request {
     size_t off = 0, bytes = 0;       // pool region
     size_t desc_off = 0;             // RunDesc, PrepDesc, DftDesc of the run
     int group = 0;                   // group_of(precision, kind, abc)
-    int hl = 0, hr = 0;
-    int64_t own = 0, ntiles = 0;
+    TileGeom geom;                   // one-wave tiles
+    int64_t ntiles = 0;
     int64_t start_block = 0, end_block = 0;
     // pinned host block: inputs at admission, results at retirement
     void *host = nullptr;
@@ -362,10 +362,9 @@ struct Server {
             return fail(GFDTD_E_NOMEM, "request needs %zu bytes, pool holds %zu",
                         rq->bytes, pool.size);
         rq->group = group_of(p->precision, p->kind, p->abc);
-        if (!halo_lanes(p->beta, Cg[p->precision], T, rq->hl, rq->hr))
+        if (!tile_geometry(p->beta, Cg[p->precision], T, 1, 1, rq->geom))
             return fail(GFDTD_E_INVALID, "block depth too large");
-        rq->own = (int64_t)(kWave - rq->hl - rq->hr) * Cg[p->precision];
-        rq->ntiles = (p->nz + rq->own - 1) / rq->own;
+        rq->ntiles = (p->nz + rq->geom.own - 1) / rq->geom.own;
         if (rq->ntiles > tile_cap)
             return fail(GFDTD_E_NOMEM, "request needs %lld tiles, tables hold %lld",
                         (long long)rq->ntiles, (long long)tile_cap);
@@ -455,8 +454,7 @@ struct Server {
             RunDesc rd;
             PrepDesc pd;
             DftDesc dd;
-            fill_run_desc(pool_base, r, p.precision, rq->hl, rq->hr, rq->own,
-                          rq->start_block, rd, pd, dd);
+            fill_run_desc(pool_base, r, p.precision, rq->geom, rq->start_block, rd, pd, dd);
             std::memcpy(h + h_desc, &rd, sizeof rd);
             std::memcpy(h + h_desc + sizeof rd, &pd, sizeof pd);
             std::memcpy(h + h_desc + sizeof rd + sizeof pd, &dd, sizeof dd);
@@ -510,8 +508,8 @@ struct Server {
             RunDesc d;
             PrepDesc pd;
             DftDesc dd;
-            fill_run_desc(pool_base, rq->r, rq->r.p.precision, rq->hl, rq->hr, rq->own,
-                          rq->start_block, d, pd, dd);
+            fill_run_desc(pool_base, rq->r, rq->r.p.precision, rq->geom, rq->start_block, d,
+                          pd, dd);
             const int m = (int)rd.size();
             rd.push_back(d);
             for (int64_t t = 0; t < rq->ntiles; ++t)
@@ -651,7 +649,7 @@ struct Server {
                         continue;
                     const int pr = group_precision(g);
                     for (int w = 0; w < (nwin[g] ? 2 : 1); ++w) {
-                        e = launch_tiles(pr, group_kind(g), group_ring(g), w == 1, Cg[pr],
+                        e = launch_tiles(pr, group_kind(g), group_ring(g), w == 1, Cg[pr], 1,
                                          reinterpret_cast<const RunDesc *>(pool_base + runs_off[cur[g]][g]),
                                          reinterpret_cast<const TileRef *>(pool_base + tiles_off[cur[g]][g]),
                                          gblock, T, ntiles[g], gs[g >> 1]);

@@ -80,7 +80,8 @@ class gfdtd_exec(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("variant", C.c_int32),
         ("cells_per_lane", C.c_int32), ("block_steps", C.c_int32),
-        ("use_graph", C.c_int32), ("reserved0", C.c_int32),
+        ("use_graph", C.c_int32), ("tile_waves", C.c_int32),
+        ("exchange_steps", C.c_int32), ("reserved0", C.c_int32),
     ]
 
 
@@ -90,7 +91,8 @@ class gfdtd_stats(C.Structure):
         ("block_steps", C.c_int32), ("graph", C.c_int32),
         ("launches", C.c_int64), ("tiles", C.c_int64),
         ("cell_updates", C.c_double), ("step_ms", C.c_double),
-        ("pass_ms", C.c_double),
+        ("pass_ms", C.c_double), ("tile_waves", C.c_int32),
+        ("exchange_steps", C.c_int32),
     ]
 
 
@@ -285,13 +287,15 @@ def _device_buffer(nbytes: int):
 
 
 def _exec_struct(variant=GFDTD_VARIANT_AUTO, cells_per_lane=0, block_steps=0,
-                 use_graph=-1):
+                 use_graph=-1, tile_waves=0, exchange_steps=0):
     e = gfdtd_exec()
     e.struct_size = C.sizeof(gfdtd_exec)
     e.variant = int(variant)
     e.cells_per_lane = int(cells_per_lane)
     e.block_steps = int(block_steps)
     e.use_graph = int(use_graph)
+    e.tile_waves = int(tile_waves)
+    e.exchange_steps = int(exchange_steps)
     return e
 
 
@@ -425,7 +429,7 @@ class Batch:
 
     def __init__(self, problems: Sequence, steps=None, variant=GFDTD_VARIANT_AUTO,
                  cells_per_lane=0, block_steps=0, use_graph=-1, stream=None,
-                 record_trace=True, fields=True):
+                 record_trace=True, fields=True, tile_waves=0, exchange_steps=0):
         import torch
         self._lib = load_library()
         self._ms, self._arr, self._st = _arrays(problems, steps)
@@ -439,7 +443,8 @@ class Batch:
             self._arr, self._st.ctypes.data_as(_PI64), len(self._ms), C.byref(n)))
         self.workspace_bytes = n.value
         self._ws = _device_buffer(n.value)
-        self._exec = _exec_struct(variant, cells_per_lane, block_steps, use_graph)
+        self._exec = _exec_struct(variant, cells_per_lane, block_steps, use_graph,
+                                  tile_waves, exchange_steps)
         h = C.c_void_p(None)
         _check(self._lib.gfdtd_batch_prepare(
             self._arr, self._st.ctypes.data_as(_PI64), len(self._ms),
@@ -459,11 +464,13 @@ class Batch:
         return [o.as_dict() for o in outs]
 
     def autotune(self, trial_blocks: int = 4) -> Dict[str, int]:
-        """Pick cells per lane and steps per launch by timing trial launches
-        on this batch (results do not depend on the choice)."""
+        """Pick cells per lane, steps per launch and waves per tile by
+        timing trial launches on this batch (results do not depend on the
+        choice)."""
         e = _exec_struct()
         _check(self._lib.gfdtd_batch_autotune(self._h, int(trial_blocks), C.byref(e)))
         return {"cells_per_lane": e.cells_per_lane, "block_steps": e.block_steps,
+                "tile_waves": e.tile_waves, "exchange_steps": e.exchange_steps,
                 "graph": e.use_graph}
 
     def stats(self) -> Dict[str, float]:

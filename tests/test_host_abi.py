@@ -46,15 +46,37 @@ def test_binding_covers_header(P):
     assert set(_declared()) == set(P.gfdtd.EXPORTS)
 
 
-def test_struct_sizes_match_header(P):
-    """The ctypes layouts match the C structs (the library rejects a
-    smaller struct_size, so a mismatch would show as E_INVALID)."""
+def test_struct_sizes_match_header(P, tmp_path):
+    """The ctypes layouts match the C structs: sizes and field offsets
+    printed by a C program compiled against the header (the library
+    rejects a smaller struct_size, so a mismatch would show as E_INVALID)."""
+    import shutil
+    import subprocess
     g = P.gfdtd
-    assert ctypes.sizeof(g.gfdtd_problem) == 4 * 8 + 8 * 3 + 8 * 2 + 8 + 6 * 8 + 8 * 4 + 8 * 4
-    assert ctypes.sizeof(g.gfdtd_result) == 8 + 8 + 5 * 8
-    assert ctypes.sizeof(g.gfdtd_exec) == 24
-    assert ctypes.sizeof(g.gfdtd_stats) == 16 + 16 + 24
-    assert ctypes.sizeof(g.gfdtd_server_config) == 16 + 24
+    structs = ["gfdtd_problem", "gfdtd_result", "gfdtd_exec", "gfdtd_stats",
+               "gfdtd_server_config", "gfdtd_tmm_stack"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gfdtd.h"',
+             "int main(void) {"]
+    for name in structs:
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in getattr(g, name)._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "sizes"
+    cc = shutil.which("gcc") or shutil.which("cc")
+    assert cc, "no C compiler"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.split() for line in
+               subprocess.run([str(exe)], check=True, capture_output=True,
+                              text=True).stdout.splitlines())
+    for name in structs:
+        t = getattr(g, name)
+        assert ctypes.sizeof(t) == int(out[name]), name
+        for f, _ in t._fields_:
+            assert getattr(t, f).offset == int(out[f"{name}.{f}"]), (name, f)
 
 
 def test_status_strings(P):
@@ -217,3 +239,24 @@ def test_tmm_stacks_validated(P):
         st, _ = check([ok, b])
         assert st == g.GFDTD_E_INVALID
         assert "stack 1" in g.load_library().gfdtd_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("cells_per_lane", 6), ("block_steps", 257), ("block_steps", -1),
+    ("tile_waves", 5), ("tile_waves", -1), ("exchange_steps", 17),
+    ("exchange_steps", -2),
+])
+def test_invalid_exec_options_rejected(P, field, value):
+    """gfdtd_batch_prepare rejects execution options outside their ranges
+    before it touches the device (null workspace and stream here)."""
+    g = P.gfdtd
+    lib = P.load_library()
+    ms, arr, st = g._arrays([_ok()], None)
+    e = g._exec_struct()
+    setattr(e, field, value)
+    h = ctypes.c_void_p(None)
+    status = lib.gfdtd_batch_prepare(arr, st.ctypes.data_as(g._PI64), 1, ctypes.byref(e),
+                                     None, 0, None, ctypes.byref(h))
+    assert status == g.GFDTD_E_INVALID
+    assert field.split("_")[0] in lib.gfdtd_last_error().decode()
+    assert not h.value
