@@ -4,13 +4,15 @@
 // temporal block of T time steps.  A tile is one 64-lane wavefront holding
 // 64*C consecutive cells in registers (C cells per lane, D and B for each);
 // neighbouring values move between lanes with wave shuffles, so a tile
-// needs no LDS and no barriers.  Tiles overlap: the per-step dependency
-// cone of eq. (10) with the Table 1 terms reaches 3 cells upwind and 1 cell
-// downwind (column a, v >= 0) or 1 upwind / 2 downwind (column b), so
-// after T steps only the lanes away from the tile edges hold valid
-// values; those "owned" lanes are written back, to the other half of a
-// ping-pong pair.  HBM traffic per cell-update is therefore about
-// 2 * 2 * sizeof(R) / T plus the halo overhead.
+// needs no LDS and no barriers.  Tiles overlap: a cell next to a tile edge
+// lacks its outside neighbour, and the error spreads by the reach of a
+// step of eq. (10) with the Table 1 terms, 2 cells upwind (plus 1 in the
+// first step) and 1 downwind, so after T steps only the lanes away from
+// the tile edges hold valid values; those "owned" lanes are written back,
+// to the other half of a ping-pong pair.  HBM traffic per cell-update is
+// therefore about 2 * 2 * sizeof(R) / T plus the halo overhead.  Optional
+// multi-wave tiles put G waves side by side and refresh the cells they
+// share through LDS every K steps (one barrier per refresh).
 //
 // Per step and cell (all in registers), with the star fields carried
 // scaled by the Courant number S (E~ = S E*, H~ = S H*):

@@ -372,15 +372,25 @@ void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
     K = (ex && ex->exchange_steps > 0) ? ex->exchange_steps : 8;
 }
 
+// Halo lanes of a T-step block.  Cells next to a wave edge lose their
+// outside neighbour (the lane shift brings in zero), and the error spreads
+// by the reach of one step: for column a (beta >= 0) D by 2 cells a step
+// upwind (left) plus 1 in the first step, B by 2, and 1 cell downwind; for
+// column b the mirror: 1 cell left, 2 right.  A probe's E at the owned
+// cell k also reads B at k-1, k-2 (column a) or k+1 (column b) after the
+// last step, and the end condition at node nz-1 (which may be the first
+// owned cell) reads D and B at nz-2.  The owned lanes must stay clear of
+// all of it: 2T + 2 cells upwind for column a and T downwind; T + 1 cells
+// left and 2T + 1 right for column b.
 bool halo_lanes(double beta, int C, int T, int &hl, int &hr)
 {
-    const int up = (3 * T + C - 1) / C, one = (T + C - 1) / C, two = (2 * T + C - 1) / C;
+    auto lanes = [C](int cells) { return (cells + C - 1) / C; };
     if (beta >= 0.0) {
-        hl = up;
-        hr = one;
+        hl = lanes(2 * T + 2);
+        hr = lanes(T);
     } else {
-        hl = one;
-        hr = two;
+        hl = lanes(T + 1);
+        hr = lanes(2 * T + 1);
     }
     return hl + hr < kWave;
 }
