@@ -97,11 +97,17 @@ def serve(P, stream, pool_bytes, max_slots, blocks_per_call=64, closed=False):
     (arrival time, problem).  closed=True submits everything at t = 0.
     Returns a dict: the seconds from the first arrival to the last
     completion, per-request latencies (s), total cell-updates, the
-    (completion time, cell-updates) of every request, and rejections."""
+    (completion time, cell-updates) of every request, rejections, and the
+    mean time a request waits for admission: by Little's law the time
+    integral of the server's queue length divided by the requests that
+    entered it."""
     lat = []
     done = []
     updates = 0
     rejected = 0
+    queue_area = 0.0
+    last_q, last_t = 0, 0.0
+    accepted = 0
     with P.Server(pool_bytes=pool_bytes, max_slots=max_slots) as srv:
         pending = {}
         i = 0
@@ -120,9 +126,13 @@ def serve(P, stream, pool_bytes, max_slots, blocks_per_call=64, closed=False):
                     continue
                 pending[rid] = (arr, prob.nz * prob.steps)
                 updates += prob.nz * prob.steps
+                accepted += 1
                 i += 1
             if pending:
-                srv.progress(max_blocks=blocks_per_call)
+                now = time.perf_counter() - t0
+                queue_area += last_q * (now - last_t)
+                _, last_q = srv.progress(max_blocks=blocks_per_call)
+                last_t = now
                 for rid in list(pending):
                     if srv.ready(rid):
                         now = time.perf_counter() - t0
@@ -135,7 +145,8 @@ def serve(P, stream, pool_bytes, max_slots, blocks_per_call=64, closed=False):
                 time.sleep(max(0.0, min(0.01, stream[i][0] - now)))
         total = time.perf_counter() - t0
     return {"total_s": total, "latency_s": lat, "updates": updates,
-            "done": sorted(done), "rejected": rejected}
+            "done": sorted(done), "rejected": rejected,
+            "queue_wait_mean_s": queue_area / max(1, accepted)}
 
 
 def saturated_rate(done, lo=0.1, hi=0.7):
@@ -182,7 +193,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-tmm", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=500)
-    ap.add_argument("--serve-loads", default="0.5,0.8",
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9,1.1",
                     help="offered loads as fractions of the saturated request "
                          "rate, comma separated")
     ap.add_argument("--serve-nz-hi", type=float, default=1e5)
@@ -302,11 +313,13 @@ def main():
                 "cell_updates_per_s": res["updates"] / res["total_s"],
                 "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+                "queue_wait_mean_ms": res["queue_wait_mean_s"] * 1e3,
                 "rejected": res["rejected"],
             })
             log(f"serving at {frac:.2f} of capacity ({rate:.1f} req/s): "
                 f"p50 {loads[-1]['p50_latency_ms']:.1f} ms p99 "
-                f"{loads[-1]['p99_latency_ms']:.1f} ms")
+                f"{loads[-1]['p99_latency_ms']:.1f} ms, mean queueing "
+                f"{loads[-1]['queue_wait_mean_ms']:.1f} ms")
         serving = {
             "saturated_cell_updates_per_s": cap,
             "saturated_requests_per_s": cap_rps,

@@ -1,0 +1,107 @@
+"""Host logic of bench.py on the CPU: the saturated-rate slope, the guard
+on the committed traffic counters, the serving driver (latencies and the
+queueing delay from the server's queue length, by Little's law) against
+a scripted stand-in server, and the one-GPU contract."""
+import os
+import subprocess
+import sys
+import types
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_saturated_rate_is_the_middle_slope():
+    # 100 equal requests finishing every 10 ms after a 1 s start-up and
+    # with a slow tail: the 10 %-70 % slope is 100 units/s
+    done = [(1.0 + 0.01 * i, 1.0) for i in range(90)] + [(5.0 + i, 1.0) for i in range(10)]
+    assert abs(bench.saturated_rate(done) - 100.0) < 1e-9
+
+
+def test_traffic_counters_only_for_their_kernel_and_tiling(tmp_path, monkeypatch):
+    v = bench.measured_traffic_per_update(12, 32)
+    assert v is not None and 0.0 < v < 16.0
+    assert bench.measured_traffic_per_update(8, 24) is None
+    other = tmp_path / "kernels.hip"
+    other.write_text("// not the profiled source\n")
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
+    assert bench.measured_traffic_per_update(12, 32) is None
+
+
+class _FakeServer:
+    """One request in service at a time, each needing `work` progress
+    calls; the rest wait in the queue."""
+
+    def __init__(self, work, **kw):
+        self.work = work
+        self.queue, self.live, self.left, self.done = [], None, 0, set()
+        self.next_id = 1
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+    def submit(self, prob):
+        rid = self.next_id
+        self.next_id += 1
+        self.queue.append(rid)
+        return rid
+
+    def progress(self, max_blocks=1):
+        if self.live is None and self.queue:
+            self.live, self.left = self.queue.pop(0), self.work
+        if self.live is not None:
+            self.left -= 1
+            if self.left == 0:
+                self.done.add(self.live)
+                self.live = None
+        return (0 if self.live is None else 1), len(self.queue)
+
+    def ready(self, rid):
+        return rid in self.done
+
+    def poll(self, rid):
+        self.done.discard(rid)
+        return {"status": 0}
+
+
+def test_serving_driver_counts_latency_and_queueing(monkeypatch):
+    clock = {"t": 0.0}
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])
+    monkeypatch.setattr(bench.time, "sleep", lambda s: None)
+    fake = _FakeServer(work=3)
+
+    def Server(**kw):
+        return fake
+
+    # each progress call takes 1 s of the fake clock
+    orig = fake.progress
+
+    def progress(max_blocks=1):
+        clock["t"] += 1.0
+        return orig(max_blocks)
+
+    fake.progress = progress
+    P = types.SimpleNamespace(Server=Server, GfdtdError=RuntimeError)
+    prob = types.SimpleNamespace(nz=10, steps=5)
+    stream = [(0.0, prob)] * 4            # four requests at t = 0
+    res = bench.serve(P, stream, 1 << 20, 8, closed=True)
+    assert res["rejected"] == 0 and len(res["latency_s"]) == 4
+    assert res["updates"] == 4 * 50
+    # served one after another, 3 s each: done at 3, 6, 9, 12 s
+    assert sorted(res["latency_s"]) == [3.0, 6.0, 9.0, 12.0]
+    # waits for admission: 0, 3, 6, 9 s (the queue, as sampled after each
+    # progress call, holds 3, 2, 1 requests for 3 s each) -> mean 4.5 s
+    assert abs(res["queue_wait_mean_s"] - 4.5) < 1e-9
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
