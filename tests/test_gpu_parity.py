@@ -212,6 +212,10 @@ def test_autotune_keeps_results_bitwise(P):
             chosen = b.autotune(trial_blocks=3)
             assert chosen["cells_per_lane"] in (4, 8, 12, 16)
             assert chosen["block_steps"] in (8, 16, 24, 32, 48, 64)
+            assert chosen["tile_waves"] in (1, 4)
+            st = b.stats()
+            assert (st["cells_per_lane"], st["block_steps"], st["tile_waves"]) == \
+                (chosen["cells_per_lane"], chosen["block_steps"], chosen["tile_waves"])
             b.run()
             got = b.collect()
         for x, y in zip(got, ref):
