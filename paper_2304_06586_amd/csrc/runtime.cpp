@@ -423,6 +423,49 @@ bool tile_geometry(double beta, int C, int T, int G, int K, TileGeom &g)
     return true;
 }
 
+// A tile that holds a whole grid with open ends needs no field halo for
+// its block depth: nothing outside the grid reaches a node inside, since
+// the end condition rewrites D at nodes 0 and nz-1 and the ghost fill
+// resets B beyond the ends from inside values every step.  The coefficient
+// windows are not reset: each move of the profile shifts them one cell and
+// brings an undefined cell in at the upwind wave edge, so that side holds
+// the block's moves, at most ceil(|beta S| T) + 1, plus the two ghost cells
+// the stencil and the probe averages read; the other side one lane.
+bool whole_grid_geometry(const gfdtd_problem &p, int C, int T, int G, int K, TileGeom &g)
+{
+    g = TileGeom{};
+    const int64_t moves = (int64_t)std::ceil(std::fabs(p.beta * p.courant) * T) + 1;
+    const int up = (int)((moves + 2 + C - 1) / C);
+    g.hl = p.beta >= 0.0 ? up : 1;
+    g.hr = p.beta >= 0.0 ? 1 : up;
+    int ov = 0;
+    if (G > 1) {
+        if (G > kMaxTileWaves || K < 1)
+            return false;
+        int xl, xr;
+        halo_lanes(p.beta, C, K, xl, xr);
+        ov = xl + xr;
+        if (xl * C > kXSlot || xr * C > kXSlot || g.hl + ov > kWave || g.hr + ov > kWave ||
+            ov + std::max(xl, xr) > kWave)
+            return false;
+        g.G = G;
+        g.xl = xl;
+        g.xr = xr;
+        g.xk = K;
+    } else if (g.hl + g.hr >= kWave) {
+        return false;
+    }
+    g.own = ((int64_t)kWave * G - (int64_t)(G - 1) * ov - g.hl - g.hr) * C;
+    return g.own >= p.nz;
+}
+
+bool run_geometry(const gfdtd_problem &p, int C, int T, int G, int K, TileGeom &g)
+{
+    if (p.abc != GFDTD_ABC_PERIODIC && whole_grid_geometry(p, C, T, G, K, g))
+        return true;
+    return tile_geometry(p.beta, C, T, G, K, g);
+}
+
 // ------------------------------------------------------------------- batch
 
 gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
@@ -577,7 +620,7 @@ gfdtd_status Batch::build_tiles(Group &G)
         RunHost &r = runs[G.members[m]];
         r.T = G.T;
         TileGeom g;
-        if (!tile_geometry(r.p.beta, G.C, G.T, G.Gw, G.K, g))
+        if (!run_geometry(r.p, G.C, G.T, G.Gw, G.K, g))
             return fail(GFDTD_E_INVALID,
                         "block of %d steps too deep for %d cells per lane "
                         "(%d-wave tiles, refresh every %d steps)",
@@ -675,7 +718,7 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                 bool ok = true;
                 TileGeom tg;
                 for (int i : G.members)
-                    ok = ok && tile_geometry(runs[i].p.beta, C, T, Gw, G.K, tg);
+                    ok = ok && run_geometry(runs[i].p, C, T, Gw, G.K, tg);
                 if (!ok)
                     continue;
                 G.C = C;

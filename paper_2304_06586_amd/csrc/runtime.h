@@ -53,6 +53,12 @@ struct TileGeom {
     int64_t own = 0;
 };
 bool tile_geometry(double beta, int C, int T, int G, int K, TileGeom &g);
+// One tile holding a whole open grid (no field halo for the block depth;
+// the upwind side holds the block's profile moves); false if the grid does
+// not fit.
+bool whole_grid_geometry(const gfdtd_problem &p, int C, int T, int G, int K, TileGeom &g);
+// The geometry a run gets: a whole-grid tile when it fits, else tile_geometry.
+bool run_geometry(const gfdtd_problem &p, int C, int T, int G, int K, TileGeom &g);
 
 // A run with host copies of its inputs.
 struct RunHost {

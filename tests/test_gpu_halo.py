@@ -71,9 +71,11 @@ def test_grid_end_at_every_owned_position(P, beta, C, T, G, K):
     """Grids whose last node nz-1 falls on every lane position around the
     edges of the owned regions (a sweep of nz), so some run has it as the
     first owned cell of a tile or wave: the end condition there reads the
-    cell to its left."""
+    cell to its left.  Runs that fit one tile take whole-grid tiles; the
+    larger ones (from about 1340 cells) cross ordinary tile and wave edges."""
     probs = []
-    for nz in list(range(340, 470)) + list(range(650, 700)) + list(range(800, 830)):
+    for nz in (list(range(340, 470)) + list(range(650, 700)) + list(range(800, 830)) +
+               list(range(1340, 1372)) + list(range(2036, 2056)) + list(range(2260, 2284))):
         p = W.small_case(nz, 2 * T, beta, structure="random", seed=nz)
         d, b = W.random_fields(nz, seed=nz + 3)
         probs.append(p.replace(init_d=d, init_b=b,
@@ -87,3 +89,48 @@ def test_grid_end_at_every_owned_position(P, beta, C, T, G, K):
         for k in ("trace", "d"):
             assert rel(got[k], want[k]) <= TOL64, (p.nz, k)
         assert rel(got["b"][:-1], want["b"][:-1]) <= TOL64, p.nz
+
+
+# One tile holding a whole open grid needs no field halo for its block
+# depth; its upwind side holds the block's profile moves (ceil(|beta S| T)
+# + 1 cells) plus two ghost cells, the other side one lane.  Here |beta S|
+# = 0.15: one wave at C = 8, T = 256 holds (64 - 6 - 1) x 8 = 456 cells; a
+# 4-wave tile at C = 12, K = 8, T = 256 holds (256 - 3 x 3 - 4 - 1) x 12 =
+# 2904.  Past the whole-grid capacity at the given depth (496 cells for one
+# wave at T = 24, 2940 for the 4-wave tile at T = 48) the usual halos apply.
+@pytest.mark.parametrize("nz,C,G,T", [(456, 8, 1, 256), (497, 8, 1, 24), (300, 8, 1, 256),
+                                      (2904, 12, 4, 256), (2941, 12, 4, 48),
+                                      (2000, 12, 4, 200)])
+@pytest.mark.parametrize("beta", [0.3, -0.3])
+def test_whole_grid_tiles_any_block_depth(P, nz, C, G, T, beta):
+    probs = []
+    for i, (kind, abc, window) in enumerate([
+            (W.MODULATION, W.ABC_MUR1, None),
+            (W.MODULATION, W.ABC_PEC, None),
+            (W.MATTER, W.ABC_MUR1, None),
+            (W.MODULATION, W.ABC_MUR1, W.TimeWindow(30.0, 140.5, 1.5, 1.0))]):
+        p = W.small_case(nz, 333, beta, kind=kind, structure="crystal", seed=nz + i,
+                         abc=abc)
+        d, b = W.random_fields(nz, seed=nz + 10 + i)
+        p = p.replace(init_d=d, init_b=b,
+                      probes=np.array([0, 1, 2, nz // 2, nz - 3, nz - 2, nz - 1]))
+        if window is not None:
+            p = p.replace(window=window)
+        probs.append(p)
+
+    def run(C_, T_, G_):
+        with P.Batch(probs, cells_per_lane=C_, block_steps=T_, tile_waves=G_,
+                     exchange_steps=8, use_graph=0) as bt:
+            bt.run()
+            return bt.collect()
+
+    deep = run(C, T, G)
+    ref = run(4, 16, 1)       # narrow tiles: no run fits one tile
+    for i, (a, b) in enumerate(zip(deep, ref)):
+        for k in ("trace", "dft", "d", "b"):
+            assert np.array_equal(a[k], b[k]), (nz, i, k)
+    for p, got in zip(probs[:2], deep[:2]):
+        want = oracle.solve(p)
+        assert rel(got["trace"], want["trace"]) <= TOL64
+        assert rel(got["d"], want["d"]) <= TOL64
+
