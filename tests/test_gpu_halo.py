@@ -134,3 +134,15 @@ def test_whole_grid_tiles_any_block_depth(P, nz, C, G, T, beta):
         assert rel(got["trace"], want["trace"]) <= TOL64
         assert rel(got["d"], want["d"]) <= TOL64
 
+
+
+def test_whole_grid_tile_count(P):
+    """A run that fits one tile is stepped as one tile per launch (C = 8,
+    T = 24, |beta S| = 0.15: capacity 62 lanes x 8 = 496 cells); a larger
+    one is split into ordinary tiles ((64 - 7 - 3) x 8 = 432 cells each)."""
+    for nz, tiles in ((300, 1), (496, 1), (600, 2)):
+        p = W.small_case(nz, 96, 0.3, structure="slab", seed=nz)
+        with P.Batch([p], cells_per_lane=8, block_steps=24, tile_waves=1,
+                     use_graph=0) as bt:
+            st = bt.stats()
+        assert st["launches"] == 4 and st["tiles"] == 4 * tiles, (nz, st)
