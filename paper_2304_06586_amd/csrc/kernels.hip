@@ -867,7 +867,7 @@ constexpr int mw_waves()
 // MW = false: four independent one-wave tiles per workgroup (G = 1).
 // MW = true: one tile of G waves per workgroup (blockDim = 64 G).
 template <typename R, int C, int KIND, bool RING, bool WIN, bool MW>
-__global__ __launch_bounds__(kWave *kWavesPerGroup)
+__global__ __launch_bounds__(kWave *(MW ? kMaxTileWaves : kWavesPerGroup))
 __attribute__((amdgpu_waves_per_eu(mw_waves<R, C, KIND, MW>()))) void k_tiles(
     const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
     int64_t block, int T, int ntiles, int G)

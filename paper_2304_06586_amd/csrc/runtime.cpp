@@ -347,23 +347,23 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 // --------------------------------------------------------------- tiling
 
 // Tiling defaults from measurements on MI355X (full-occupancy launches of
-// the 4096-run crystal batch): FP32 12 cells per lane and 32 steps per
-// launch, FP64 8 and 32 (FP64 holds twice the registers per cell); 4 cells
-// per lane and 24 steps when the group holds few cells (more, narrower
-// tiles keep more SIMDs busy).
+// the 4096-run crystal batch, the autotuner's choice there): FP32 16 cells
+// per lane and 48 steps per launch, FP64 12 and 48 (FP64 holds twice the
+// registers per cell); 4 cells per lane and 24 steps when the group holds
+// few cells (more, narrower tiles keep more SIMDs busy).
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
                    int64_t total_cells, bool ring, int &C, int &T, int &G, int &K)
 {
     const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
     const bool small = total_cells < (int64_t)4 << 20;
     C = (ex && ex->cells_per_lane) ? ex->cells_per_lane
-                                   : (small ? 4 : (precision == GFDTD_F32 ? 12 : 8));
+                                   : (small ? 4 : (precision == GFDTD_F32 ? 16 : 12));
     if (variant == GFDTD_VARIANT_STEP)
         T = 1;
     else if (ex && ex->block_steps > 0)
         T = ex->block_steps;
     else
-        T = small ? 24 : 32;
+        T = small ? 24 : 48;
     if (max_steps > 0 && T > max_steps)
         T = (int)std::max<int64_t>(1, max_steps);
     G = (ex && ex->tile_waves > 0) ? ex->tile_waves : 1;

@@ -22,13 +22,16 @@ def test_saturated_rate_is_the_middle_slope():
 
 
 def test_traffic_counters_only_for_their_kernel_and_tiling(tmp_path, monkeypatch):
-    v = bench.measured_traffic_per_update(12, 32)
+    fields = dict(line.split(": ") for line in open(bench.COUNTERS).read().splitlines()
+                  if line and not line.startswith("#"))
+    C, T = int(fields["cells_per_lane"]), int(fields["block_steps"])
+    v = bench.measured_traffic_per_update(C, T)
     assert v is not None and 0.0 < v < 16.0
-    assert bench.measured_traffic_per_update(8, 24) is None
+    assert bench.measured_traffic_per_update(C, T + 8) is None
     other = tmp_path / "kernels.hip"
     other.write_text("// not the profiled source\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
-    assert bench.measured_traffic_per_update(12, 32) is None
+    assert bench.measured_traffic_per_update(C, T) is None
 
 
 class _FakeServer:
