@@ -193,7 +193,7 @@ struct Server {
     char *pool_base = nullptr;
     size_t pool_bytes = 0;
     int max_slots = 1;
-    int Cg[2] = {12, 8};             // cells per lane by precision
+    int Cg[2] = {16, 8};             // cells per lane by precision
     int T = 32;
     Pool pool;
     size_t tables_bytes = 0;
@@ -300,12 +300,13 @@ struct Server {
         pool_base = static_cast<char *>(cfg->pool);
         pool_bytes = cfg->pool_bytes;
         max_slots = cfg->max_slots;
-        // Tiling on the serving mix (measured, saturated rate): FP32 12
-        // cells per lane, FP64 8 (twice the registers per cell), 32 steps
-        // per block, as for batches; 8 cells and 24 steps served 17 % less.
-        Cg[0] = 12;
+        // Tiling on the serving mix (measured, saturated rate): FP32 16
+        // cells per lane, FP64 8 (twice the registers per cell), 48 steps
+        // per block; 12 cells and 32 steps served 7 % less, 8 and 24 a
+        // further 17 % less.
+        Cg[0] = 16;
         Cg[1] = 8;
-        T = cfg->block_steps > 0 ? cfg->block_steps : 32;
+        T = cfg->block_steps > 0 ? cfg->block_steps : 48;
         if (cfg->max_ahead < 0)
             return fail(GFDTD_E_INVALID, "max_ahead must be >= 0");
         max_ahead = cfg->max_ahead > 0 ? cfg->max_ahead : 8;
