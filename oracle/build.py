@@ -11,15 +11,20 @@ SRC = os.path.join(HERE, "stepper.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
+def compile_stepper(src: str, out: str, verbose: bool = False) -> str:
+    """Compile a stepper source file into the shared library `out`."""
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-Wextra", SRC, "-o", tmp, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wextra", src, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    return compile_stepper(SRC, LIB, verbose)
 
 
 if __name__ == "__main__":

@@ -45,17 +45,23 @@ _lib = None
 _lock = threading.Lock()
 
 
+def load(path: str):
+    """A stepper library at `path` (the oracle's own, or a test's variant
+    compiled by build.compile_stepper), ready for solve(..., lib=...)."""
+    lib = C.CDLL(path)
+    lib.oracle_solve.argtypes = [C.POINTER(_Problem), C.c_int64,
+                                 C.POINTER(_Result)]
+    lib.oracle_solve.restype = C.c_int
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(_build.LIB):
                 _build.build()
-            lib = C.CDLL(_build.LIB)
-            lib.oracle_solve.argtypes = [C.POINTER(_Problem), C.c_int64,
-                                         C.POINTER(_Result)]
-            lib.oracle_solve.restype = C.c_int
-            _lib = lib
+            _lib = load(_build.LIB)
     return _lib
 
 
@@ -68,7 +74,7 @@ def _ptr(a: Optional[np.ndarray], ctype=_P_D):
 def solve(problem, steps: Optional[int] = None,
           init_d: Optional[np.ndarray] = None,
           init_b: Optional[np.ndarray] = None,
-          fields: bool = True) -> Dict[str, np.ndarray]:
+          fields: bool = True, lib=None) -> Dict[str, np.ndarray]:
     """Run the FP64 oracle on a workloads.Problem.
 
     Returns a dict with 'trace' (nprobe, steps), 'dft' (nprobe, nfreq,
@@ -76,7 +82,7 @@ def solve(problem, steps: Optional[int] = None,
     The initial fields default to the problem's init_d / init_b (zero when
     absent).
     """
-    lib = _load()
+    lib = _load() if lib is None else lib
     p = problem
     if init_d is None:
         init_d = getattr(p, "init_d", None)

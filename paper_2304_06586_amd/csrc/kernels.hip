@@ -864,7 +864,7 @@ constexpr int mw_waves()
     return (MW && sizeof(R) == 4 && C == 12 && KIND == GFDTD_MODULATION) ? 5 : 1;
 }
 
-// MW = false: four independent one-wave tiles per workgroup (G = 1).
+// MW = false: kWavesPerGroup independent one-wave tiles per workgroup (one).
 // MW = true: one tile of G waves per workgroup (blockDim = 64 G).
 template <typename R, int C, int KIND, bool RING, bool WIN, bool MW>
 __global__ __launch_bounds__(kWave *(MW ? kMaxTileWaves : kWavesPerGroup))

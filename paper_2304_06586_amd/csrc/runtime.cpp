@@ -677,9 +677,20 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
     gfdtd_status st;
     if (trial < 1)
         trial = 4;
-    hipEvent_t t0, t1;
-    if ((e = hipEventCreate(&t0)) || (e = hipEventCreate(&t1)))
+    // trial timing events, destroyed on every return path
+    struct Events {
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        ~Events()
+        {
+            if (t0)
+                (void)hipEventDestroy(t0);
+            if (t1)
+                (void)hipEventDestroy(t1);
+        }
+    } evs;
+    if ((e = hipEventCreate(&evs.t0)) || (e = hipEventCreate(&evs.t1)))
         return hip_fail(e, "create events");
+    hipEvent_t t0 = evs.t0, t1 = evs.t1;
     for (auto &G : groups) {
         double cells = 0.0, steps = 0.0;
         int neg = 0;
@@ -782,8 +793,6 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         g_tune_cache[key] = {bestC, bestT, bestG};
     }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     if ((e = hipStreamSynchronize(stream)))
         return hip_fail(e, "autotune");
     count_launches();
@@ -1155,6 +1164,11 @@ void Batch::stats(gfdtd_stats *s) const
 
 Batch::~Batch()
 {
+    // kernels or uploads of this batch may still be running on its stream
+    // (a destroy without collect, or an error path): the caller frees the
+    // workspace, and this object the upload sources, right after
+    if (stream)
+        (void)hipStreamSynchronize(stream);
     for (int k = 0; k < 3; ++k) {
         if (execs[k])
             (void)hipGraphExecDestroy(execs[k]);
