@@ -235,6 +235,26 @@ gfdtd_status gfdtd_solve(const gfdtd_problem *p, int64_t steps, void *ws,
                          size_t ws_bytes, void *stream, gfdtd_result *out);
 
 /*
+ * Allocation-free single solve, for callers that cannot allocate device
+ * memory (serving loops and harnesses that forbid allocation): the same
+ * validation, pre-flight, kernels and results as gfdtd_solve (bit for bit),
+ * with the workspace taken from a fixed device array of
+ * GFDTD_STATIC_WORKSPACE_BYTES that the library holds on every GPU it runs
+ * on until the process ends.  The call makes no device allocation and
+ * creates no events, streams or graphs; it is synchronous on `stream`
+ * (so it cannot be captured into a graph).
+ * Returns GFDTD_E_NOMEM, before any device call, when the problem's
+ * workspace (gfdtd_workspace_bytes) exceeds the array.  All calls on one
+ * GPU share its array: calls from one process are serialised per device;
+ * concurrent use of the array from outside this entry point would race.
+ * Each call rewrites every part of the array it reads, so nothing carries
+ * over from the previous call.
+ */
+#define GFDTD_STATIC_WORKSPACE_BYTES ((size_t)32 << 20)
+gfdtd_status gfdtd_solve_static(const gfdtd_problem *p, int64_t steps,
+                                void *stream, gfdtd_result *out);
+
+/*
  * Many independent solves in one pass: the runs are packed into one run
  * table and every launch advances all live runs by one temporal block.
  * outs[i] receives run i's results; its run_status reports a blow-up of

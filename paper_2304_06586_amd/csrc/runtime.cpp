@@ -587,10 +587,12 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         return hip_fail(e, "prepare");
     for (auto &r : runs)
         cell_updates += (double)r.p.nz * (double)r.steps;
+    count_launches();
+    if (no_alloc)
+        return GFDTD_OK;
     if ((e = hipEventCreate(&ev[0])) || (e = hipEventCreate(&ev[1])) ||
         (e = hipEventCreate(&ev[2])) || (e = hipEventCreate(&ev[3])))
         return hip_fail(e, "create events");
-    count_launches();
     if (use_graph == 1 || (use_graph < 0 && auto_graph()))
         return build_graphs();
     return GFDTD_OK;
@@ -1007,7 +1009,7 @@ gfdtd_status Batch::build_graphs()
 gfdtd_status Batch::run()
 {
     hipError_t e;
-    if ((e = hipEventRecord(ev[0], stream)))
+    if (ev[0] && (e = hipEventRecord(ev[0], stream)))
         return hip_fail(e, "record event");
     gfdtd_status st;
     if (graph_on) {
@@ -1016,21 +1018,23 @@ gfdtd_status Batch::run()
     } else if ((st = enqueue_zero(stream)) != GFDTD_OK) {
         return st;
     }
-    (void)hipEventRecord(ev[1], stream);
+    if (ev[1])
+        (void)hipEventRecord(ev[1], stream);
     if (graph_on) {
         if ((e = hipGraphLaunch(execs[1], stream)))
             return hip_fail(e, "launch step graph");
     } else if ((st = enqueue_steps(stream)) != GFDTD_OK) {
         return st;
     }
-    (void)hipEventRecord(ev[2], stream);
+    if (ev[2])
+        (void)hipEventRecord(ev[2], stream);
     if (graph_on) {
         if ((e = hipGraphLaunch(execs[2], stream)))
             return hip_fail(e, "launch DFT graph");
     } else if ((st = enqueue_dft(stream)) != GFDTD_OK) {
         return st;
     }
-    if ((e = hipEventRecord(ev[3], stream)))
+    if (ev[3] && (e = hipEventRecord(ev[3], stream)))
         return hip_fail(e, "record event");
     ran = true;
     return GFDTD_OK;
@@ -1153,7 +1157,7 @@ void Batch::stats(gfdtd_stats *s) const
     s->cell_updates = cell_updates;
     s->step_ms = 0.0;
     s->pass_ms = 0.0;
-    if (ran && hipEventSynchronize(ev[3]) == hipSuccess) {
+    if (ran && ev[3] && hipEventSynchronize(ev[3]) == hipSuccess) {
         float a = 0.f, b = 0.f;
         (void)hipEventElapsedTime(&a, ev[1], ev[2]);
         (void)hipEventElapsedTime(&b, ev[0], ev[3]);

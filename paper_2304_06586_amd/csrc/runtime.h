@@ -113,6 +113,9 @@ struct Batch {
     std::vector<Group> groups;
     int use_graph = -1;
     bool graph_on = false;
+    // No events, graphs or streams are created (the allocation-free entry
+    // point); stats then report no device times.
+    bool no_alloc = false;
     bool ran = false;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graphs[3] = {nullptr, nullptr, nullptr};

@@ -43,6 +43,7 @@ GFDTD_FLAG_RECORD_TRACE = 1
 GFDTD_FLAG_ALLOW_UNSTABLE = 2
 GFDTD_FLAG_KEEP_FIELDS = 4
 GFDTD_FLAG_TIME_WINDOW = 8
+GFDTD_STATIC_WORKSPACE_BYTES = 32 << 20
 GFDTD_VARIANT_AUTO = 0
 GFDTD_VARIANT_STEP = 1
 GFDTD_VARIANT_TILED = 2
@@ -135,6 +136,8 @@ EXPORTS = {
                                               C.c_int32, C.POINTER(C.c_size_t)]),
     "gfdtd_solve": (C.c_int, [C.POINTER(gfdtd_problem), C.c_int64, C.c_void_p,
                               C.c_size_t, C.c_void_p, C.POINTER(gfdtd_result)]),
+    "gfdtd_solve_static": (C.c_int, [C.POINTER(gfdtd_problem), C.c_int64, C.c_void_p,
+                                     C.POINTER(gfdtd_result)]),
     "gfdtd_solve_batch": (C.c_int, [C.POINTER(gfdtd_problem), _PI64, C.c_int32,
                                     C.c_void_p, C.c_size_t, C.c_void_p,
                                     C.POINTER(gfdtd_result)]),
@@ -360,6 +363,20 @@ def gfdtd_solve(problem, steps: Optional[int] = None, stream=None,
     out = _ResultBuffers(m, fields)
     _check(lib.gfdtd_solve(C.byref(m.struct), m.steps, C.c_void_p(ws.data_ptr()),
                            n.value, _stream_handle(stream), C.byref(out.struct)))
+    return out.as_dict()
+
+
+def gfdtd_solve_static(problem, steps: Optional[int] = None, stream=None,
+                       fields: bool = True) -> Dict[str, np.ndarray]:
+    """gfdtd_solve without a caller workspace: the library's fixed device
+    array (GFDTD_STATIC_WORKSPACE_BYTES per GPU) serves as the workspace and
+    no device memory is allocated.  Same results as gfdtd_solve."""
+    lib = load_library()
+    m = _Marshalled(problem, steps)
+    m.struct.flags |= GFDTD_FLAG_RECORD_TRACE
+    out = _ResultBuffers(m, fields)
+    _check(lib.gfdtd_solve_static(C.byref(m.struct), m.steps, _stream_handle(stream),
+                                  C.byref(out.struct)))
     return out.as_dict()
 
 
