@@ -101,6 +101,27 @@ __device__ __forceinline__ R from_lane(R v, int src)
     return __shfl(v, src, kWave);
 }
 
+// Lane l's value of v, for a wave-uniform l (v_readlane, no LDS).
+__device__ __forceinline__ int readlane_i(int v, int l)
+{
+    return __builtin_amdgcn_readlane(v, l);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = readlane_i((int)(u & 0xffffffffLL), l);
+    const int hi = readlane_i((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
+{
+    const int lo = readlane_i((int)(v & 0xffffffffLL), l);
+    const int hi = readlane_i((int)(v >> 32), l);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ int64_t profile_shift(double bS, double tau)
 {
     return (int64_t)rint(bS * tau);
@@ -499,21 +520,20 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
     };
 
-    bool ownsProbe = false;
-    for (int q = 0; q < nprobe; ++q) {
-        const int64_t kp = rd->probes[q];
-        ownsProbe = ownsProbe || (kp >= own_lo && kp < own_hi);
-    }
+    // Lane q holds the cell of probe q (at most 64 probes); bit q of pmask
+    // says this tile owns it.  The per-step recording then reads no memory.
+    const int64_t kpl = lane < nprobe ? rd->probes[lane] : (int64_t)-1;
+    const uint64_t pmask = __ballot(lane < nprobe && kpl >= own_lo && kpl < own_hi);
+    const bool ownsProbe = pmask != 0ull;
 
     // Physical E = E* + beta Bbar at the owned probes, for time n-1/2
     // (E* = E~ / S).
     auto record = [&](int64_t n) __attribute__((always_inline)) {
         if (n < 2 || !ownsProbe)
             return;
-        for (int q = 0; q < nprobe; ++q) {
-            const int64_t kp = rd->probes[q];
-            if (kp < own_lo || kp >= own_hi)
-                continue;
+        for (uint64_t m = pmask; m != 0ull; m &= m - 1ull) {
+            const int q = (int)__builtin_ctzll(m);
+            const int64_t kp = readlane_i64(kpl, q);
             const int lp = (int)((kp - x0) / C);
             const int cp = (int)((kp - x0) % C);
             const R e = pick<R, C>(Es, cp);
@@ -539,10 +559,15 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             shift_window<R, C, NEG>(gh);
     };
 
+    // Per-step scalars of the full step, loaded once per 64-step chunk with
+    // lane j holding step j of the chunk (FP64, rounded to R where used):
+    // the source sample and the end coefficients.
+    double srcv = 0.0, cLv = 0.0, cRv = 0.0;
+
     // One time step n with fixed coefficient windows, from (Di, Bi) to
-    // (Dn, Bn); mEn is the profile shift at the E time n+1/2 and onEn
-    // whether the profile exists then (read by the end conditions only).
-    auto one_step = [&](auto edge_tag, int64_t n, int mEn, bool onEn,
+    // (Dn, Bn); q is the step's index within its chunk (the lane that
+    // holds its source sample and end coefficients).
+    auto one_step = [&](auto edge_tag, int64_t n, int q,
                         const R (&Di)[C], const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
                         __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
@@ -626,7 +651,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
         // soft source
         if (kEdge && hasSrc && n <= rd->nsrc) {
-            const R g = (R)rd->src[n - 1];
+            const R g = (R)readlane_d(srcv, q);
             if constexpr (RING) {
                 if (smask) {
 #pragma unroll
@@ -646,8 +671,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int l0 = (int)(-x0 / C);
             if (lane == l0) {
                 if (abc == GFDTD_ABC_MUR1) {
-                    const R cL = onEn ? (R)rd->murL[clampi(-mEn, 0, nz - 1)]
-                                      : (R)rd->murB;
+                    const R cL = (R)readlane_d(cLv, q);
                     Dn[0] = Di[1] + cL * (Dn[1] - Di[0]);
                 } else {
                     Dn[0] = (R)0;
@@ -660,8 +684,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int cr = (int)(r % C);
             const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
-            const R cR = onEn ? (R)rd->murR[clampi(nz - 1 - mEn, 0, nz - 1)]
-                              : (R)rd->murB;
+            const R cR = (R)readlane_d(cRv, q);
             if (lane == lr) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
@@ -759,6 +782,22 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                               profile_shift32(bS64, tn + 0.5) != profile_shift32(bS64, tn - 0.5);
             const uint64_t hmask = __ballot(hbit);
             const uint64_t emask = __ballot(ebit);
+            if constexpr (kEdge) {
+                // this lane's step n = n0 + sl: its source sample and, at
+                // the E time n+1/2, the end coefficients of the medium then
+                // under the end nodes (the background one while a time
+                // window has the profile off)
+                const int64_t nl = n0 + sl;
+                srcv = (hasSrc && sl < nsub && nl <= rd->nsrc) ? rd->src[nl - 1] : 0.0;
+                if ((touchL || touchR) && abc == GFDTD_ABC_MUR1 && sl < nsub) {
+                    const int mEl = profile_shift32(bS64, tn + 0.5);
+                    const bool onl = !windowed || active(tn + 0.5);
+                    if (touchL)
+                        cLv = onl ? rd->murL[clampi(-mEl, 0, nz - 1)] : rd->murB;
+                    if (touchR)
+                        cRv = onl ? rd->murR[clampi(nz - 1 - mEl, 0, nz - 1)] : rd->murB;
+                }
+            }
             // finite-duration modulation: bit j of hsw / esw = the H / E
             // window switches (on or off) before / after step j; hact /
             // eact = the profile exists at the H time of step j / at the
@@ -797,20 +836,13 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 const int stop = rest ? j + (int)__builtin_ctzll(rest) : len - 1;
                 // two steps at a time, ping-ponging between register sets
                 // (D, B) and (D2, B2), so no copies between steps
-                auto mEn_of = [&](int q) __attribute__((always_inline)) {
-                    return mEc + (((emask >> q) & 1ull) ? dir : 0);
-                };
-                auto on_of = [&](int q) __attribute__((always_inline)) {
-                    return ((eact >> q) & 1ull) != 0;
-                };
                 int q = j;
                 for (; q + 1 <= stop; q += 2) {
-                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), on_of(q), D, B, D2, B2);
-                    one_step(edge_tag, n0 + s0 + q + 1, mEn_of(q + 1), on_of(q + 1),
-                             D2, B2, D, B);
+                    one_step(edge_tag, n0 + s0 + q, q, D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q + 1, q + 1, D2, B2, D, B);
                 }
                 if (q <= stop) {
-                    one_step(edge_tag, n0 + s0 + q, mEn_of(q), on_of(q), D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q, q, D, B, D2, B2);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         D[c] = D2[c];

@@ -4,8 +4,12 @@ the same seeded inputs.
 Tolerances (relative L2 over each output):
   FP64 path: 1e-12 -- the kernels use reciprocal coefficients and fused
              multiply-adds, so they differ from the oracle only in rounding;
-  FP32 path: 1e-4  -- FP32 storage and stencil arithmetic; the measured
-             error is printed per case (typically 1e-7 .. 1e-5).
+  FP32 path: 1e-5 on the oracle-sized cases -- FP32 storage and stencil
+             arithmetic; the error is printed per case.  Full-size FP32 runs
+             are held to a bound from the arithmetic (fp32_bound below).
+Final fields of a run whose pulse has left the grid are a residual far
+below the pulse, so at full size they are compared by the largest
+deviation relative to the largest field the run's probes recorded.
 Bit-for-bit on the GPU side: results do not depend on the tiling, the
 temporal block depth, graph capture or the batch they run in.
 """
@@ -20,7 +24,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 1e-4
+TOL32 = 1e-5
 
 
 def rel(a, b):
@@ -54,6 +58,26 @@ def compare(got, want, tol, label=""):
         assert v <= tol, (label, k, v)
     assert got["status"] == 0
     return errs
+
+
+def fp32_bound(p):
+    """Bound on the relative error of an FP32 run's probe trace and spectra
+    against the FP64 oracle.  Coefficients rounded to FP32 (relative error
+    u = 2^-24 each) change the local wave speed by at most u and unbalance
+    the velocity terms by at most |beta| u, so a carrier at omega picks up
+    a phase error of at most u (1 + |beta|) omega t after travelling for a
+    time t (sum of k dz over the path = omega t, whatever the medium); the
+    stencil's own roundings, about ten per cell and step, add a random walk
+    of about u (10 N)^(1/2) over N steps.  Four times the sum."""
+    u = 2.0 ** -24
+    t = p.steps * p.courant
+    return 4.0 * u * ((1.0 + abs(p.beta)) * p.pulse.omega * t + np.sqrt(10.0 * p.steps))
+
+
+def field_dev(got, want, peak):
+    """Largest deviation of a final field relative to the run's peak probe
+    field."""
+    return float(np.max(np.abs(np.asarray(got) - np.asarray(want))) / peak)
 
 
 def run(P, p, **exec_kw):
@@ -114,6 +138,30 @@ def test_tilings_agree_bitwise_and_match_oracle(P, C, T, beta):
     for k in ("trace", "dft", "d", "b"):
         assert np.array_equal(got[k], ref[k]), (C, T, k)
     compare(got, oracle.solve(p), TOL64, f"C={C} T={T}")
+
+
+_TILING_ORACLE = {}
+
+
+@pytest.mark.parametrize("C,T", [(12, 24), (12, 48), (16, 24), (16, 48), (4, 24), (8, 48)])
+@pytest.mark.parametrize("beta", [0.35, -0.3])
+@pytest.mark.parametrize("kind", [W.MODULATION, W.MATTER])
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_one_wave_tilings_by_kind_and_precision(P, C, T, beta, kind, precision):
+    """One-wave tiles at every cells-per-lane the tuner may pick, shallow
+    and deep blocks, both kinds, both precisions and both signs of v: the
+    same bits as one step per launch at 8 cells per lane, and the oracle."""
+    p = W.small_case(4321, 500, beta, kind=kind, structure="crystal", seed=7, nprobe=5,
+                     precision=precision)
+    ref = run(P, p, cells_per_lane=8, block_steps=1, tile_waves=1, use_graph=0)
+    got = run(P, p, cells_per_lane=C, block_steps=T, tile_waves=1, use_graph=0)
+    for k in ("trace", "dft", "d", "b"):
+        assert np.array_equal(got[k], ref[k]), (C, T, k)
+    key = (kind, beta)
+    if key not in _TILING_ORACLE:
+        _TILING_ORACLE[key] = oracle.solve(p)
+    tol = TOL64 if precision == W.F64 else TOL32
+    compare(got, _TILING_ORACLE[key], tol, f"C={C} T={T} k={kind} b={beta} p={precision}")
 
 
 def test_graph_capture_matches_plain_launches(P):
@@ -277,23 +325,69 @@ def test_full_crystal_batch_in_benchmark_configuration(P):
         assert e < TOL32
 
 
-def test_slab_full_size_fp64(P):
-    """The 65536-cell moving slab for all 131072 steps (8.6e9 cell-updates)
-    in FP64 against the oracle.  The probe trace and spectra are held to the
-    FP64 tolerance.  By the end the pulse has left through the absorbing
-    ends and the final fields are a residual of about 1e-4 of the pulse, so
-    their rounding differences, relative to that residual, read ~1e4 times
-    larger: they are held to 1e-10."""
+@pytest.fixture(scope="module")
+def slab_reference():
+    """The oracle on the full 65536-cell, 131072-step moving slab (8.6e9
+    cell-updates), shared by the FP64 and FP32 checks."""
     p = W.slab_run(0)
+    return p, oracle.solve(p)
+
+
+def test_slab_full_size_fp64(P, slab_reference):
+    """The 65536-cell moving slab for all 131072 steps in FP64 against the
+    oracle.  The probe trace and spectra are held to the FP64 tolerance.  By
+    the end the pulse has left through the absorbing ends and the final
+    fields are a residual of about 1e-4 of the pulse, so they are compared
+    by their largest deviation relative to the run's peak probe field, also
+    at the FP64 tolerance."""
+    p, want = slab_reference
     got = P.gfdtd_solve(p)
-    want = oracle.solve(p)
+    peak = float(np.max(np.abs(want["trace"])))
     e_tr = rel(got["trace"], want["trace"])
     e_dft = rel(got["dft"], want["dft"])
-    e_d = rel(got["d"], want["d"])
-    e_b = rel(got["b"][:-1], want["b"][:-1])
-    print(f"slab 65536x131072 f64: trace={e_tr:.2e} dft={e_dft:.2e} d={e_d:.2e} b={e_b:.2e}; "
-          f"final |d| / peak probe = {np.max(np.abs(want['d'])) / np.max(np.abs(want['trace'])):.1e}",
-          flush=True)
+    e_d = field_dev(got["d"], want["d"], peak)
+    e_b = field_dev(got["b"][:-1], want["b"][:-1], peak)
+    print(f"slab 65536x131072 f64: trace={e_tr:.2e} dft={e_dft:.2e} "
+          f"max|dd|/peak={e_d:.2e} max|db|/peak={e_b:.2e}; "
+          f"final |d| / peak probe = {np.max(np.abs(want['d'])) / peak:.1e}", flush=True)
     assert got["status"] == 0
     assert e_tr <= TOL64 and e_dft <= TOL64
-    assert e_d <= 1e-10 and e_b <= 1e-10
+    assert e_d <= TOL64 and e_b <= TOL64
+
+
+def test_slab_full_size_fp32(P, slab_reference):
+    """The same slab in FP32 (FP64 shifts, coefficients before rounding,
+    source, probes and DFT) against the FP64 oracle, held to the
+    arithmetic bound of the FP32 path."""
+    p64, want = slab_reference
+    p = p64.replace(precision=W.F32)
+    got = P.gfdtd_solve(p)
+    peak = float(np.max(np.abs(want["trace"])))
+    e_tr = rel(got["trace"], want["trace"])
+    e_dft = rel(got["dft"], want["dft"])
+    e_d = field_dev(got["d"], want["d"], peak)
+    bound = fp32_bound(p)
+    print(f"slab 65536x131072 f32: trace={e_tr:.2e} dft={e_dft:.2e} "
+          f"max|dd|/peak={e_d:.2e} (bound {bound:.2e})", flush=True)
+    assert got["status"] == 0
+    assert e_tr <= bound and e_dft <= bound and e_d <= bound
+
+
+def test_crystal_batch_largest_runs_full_length(P):
+    """The eight longest runs of the 4096-run crystal batch (nz near 65536,
+    about 2.6e5 steps each, 1.3e11 cell-updates), batched in FP32 at their
+    full step counts, against the FP64 oracle (one host thread per run)."""
+    probs = W.crystal_runs(0, count=4096, precision=W.F32)
+    order = np.argsort([-(q.nz * q.steps) for q in probs])[:8]
+    sel = [probs[i] for i in order]
+    got = P.gfdtd_solve_batch(sel, fields=False)
+    threads = min(8, os.cpu_count() or 1)
+    want = oracle.solve_many([q.replace(precision=W.F64) for q in sel], threads=threads)
+    for i, q, g, r in zip(order, sel, got, want):
+        e_tr = rel(g["trace"], r["trace"])
+        e_dft = rel(g["dft"], r["dft"])
+        bound = fp32_bound(q)
+        print(f"crystal run {i}: nz={q.nz} steps={q.steps} beta={q.beta:.3f} f32: "
+              f"trace={e_tr:.2e} dft={e_dft:.2e} (bound {bound:.2e})", flush=True)
+        assert g["status"] == 0
+        assert e_tr <= bound and e_dft <= bound
