@@ -398,6 +398,11 @@ gfdtd_status gfdtd_tmm_workspace_bytes(const gfdtd_tmm_stack *stacks,
 gfdtd_status gfdtd_tmm(const gfdtd_tmm_stack *stacks, int32_t nstacks,
                        const double *omegas, int32_t nomega, void *ws,
                        size_t ws_bytes, void *stream, double *t, double *gamma);
+/* Device time in ms of the transfer-matrix kernel alone in the calling
+ * thread's last successful gfdtd_tmm (HIP events around the launch, on its
+ * stream; the call itself also packs the stacks on the host and copies them
+ * and the results).  GFDTD_E_INVALID if there is none. */
+gfdtd_status gfdtd_tmm_kernel_ms(double *ms);
 
 #ifdef __cplusplus
 }

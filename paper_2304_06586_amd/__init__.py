@@ -10,5 +10,5 @@ from .gfdtd import (  # noqa: F401
     Batch, GfdtdError, Server, gfdtd_batch_workspace_bytes, gfdtd_check,
     gfdtd_result_sizes, gfdtd_solve, gfdtd_solve_batch, gfdtd_solve_static,
     gfdtd_status_str,
-    gfdtd_tmm, gfdtd_workspace_bytes, load_library,
+    gfdtd_tmm, gfdtd_tmm_kernel_ms, gfdtd_workspace_bytes, load_library,
 )

@@ -95,16 +95,15 @@ __device__ __forceinline__ double fmad(double a, double b, double c)
     return __builtin_fma(a, b, c);
 }
 
-template <typename R>
-__device__ __forceinline__ R from_lane(R v, int src)
-{
-    return __shfl(v, src, kWave);
-}
-
 // Lane l's value of v, for a wave-uniform l (v_readlane, no LDS).
 __device__ __forceinline__ int readlane_i(int v, int l)
 {
     return __builtin_amdgcn_readlane(v, l);
+}
+
+__device__ __forceinline__ float readlane_r(float v, int l)
+{
+    return __int_as_float(readlane_i(__float_as_int(v), l));
 }
 
 __device__ __forceinline__ double readlane_d(double v, int l)
@@ -114,6 +113,8 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     const int hi = readlane_i((int)(u >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+__device__ __forceinline__ double readlane_r(double v, int l) { return readlane_d(v, l); }
 
 __device__ __forceinline__ int64_t readlane_i64(int64_t v, int l)
 {
@@ -441,7 +442,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     auto ghosts = [&](R (&Bv)[C]) __attribute__((always_inline)) {
         if (touchL) {
             const int l0 = (int)(-x0 / C);
-            const R b0 = from_lane(Bv[0], l0);
+            const R b0 = readlane_r(Bv[0], l0);
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (kb + c < 0)
@@ -449,7 +450,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
         if (touchR) {
             const int64_t r = nz - 2 - x0;
-            const R bl = from_lane(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
+            const R bl = readlane_r(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (kb + c >= nz - 1)
@@ -520,15 +521,16 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
     };
 
-    // Lane q holds the cell of probe q (at most 64 probes); bit q of pmask
-    // says this tile owns it.  The per-step recording then reads no memory.
-    const int64_t kpl = lane < nprobe ? rd->probes[lane] : (int64_t)-1;
-    const uint64_t pmask = __ballot(lane < nprobe && kpl >= own_lo && kpl < own_hi);
-    const bool ownsProbe = pmask != 0ull;
+    bool ownsProbe = false;
+    for (int q = 0; q < nprobe; ++q) {
+        const int64_t kp = rd->probes[q];
+        ownsProbe = ownsProbe || (kp >= own_lo && kp < own_hi);
+    }
 
     // Physical E = E* + beta Bbar at the owned probes, for time n-1/2
-    // (E* = E~ / S).
-    auto record = [&](int64_t n) __attribute__((always_inline)) {
+    // (E* = E~ / S); lane q of kpl holds the cell of probe q and bit q of
+    // pmask says this tile owns it.
+    auto record = [&](int64_t n, int64_t kpl, uint64_t pmask) __attribute__((always_inline)) {
         if (n < 2 || !ownsProbe)
             return;
         for (uint64_t m = pmask; m != 0ull; m &= m - 1ull) {
@@ -559,15 +561,11 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             shift_window<R, C, NEG>(gh);
     };
 
-    // Per-step scalars of the full step, loaded once per 64-step chunk with
-    // lane j holding step j of the chunk (FP64, rounded to R where used):
-    // the source sample and the end coefficients.
-    double srcv = 0.0, cLv = 0.0, cRv = 0.0;
-
     // One time step n with fixed coefficient windows, from (Di, Bi) to
-    // (Dn, Bn); q is the step's index within its chunk (the lane that
-    // holds its source sample and end coefficients).
-    auto one_step = [&](auto edge_tag, int64_t n, int q,
+    // (Dn, Bn).  The full step also takes the step's source sample gsrc and
+    // end coefficients cL, cR, and the probe cells (kpl, pmask as in record).
+    auto one_step = [&](auto edge_tag, int64_t n, R gsrc, R cL, R cR, int64_t kpl,
+                        uint64_t pmask,
                         const R (&Di)[C], const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
                         __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
@@ -583,7 +581,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         if constexpr (!kMatter) {
             if constexpr (kEdge) {
                 compute_es(Di, Bi);
-                record(n);
+                record(n, kpl, pmask);
             }
             if constexpr (!NEG) {
                 const R Bm1 = from_left(Bi[C - 1]);
@@ -605,7 +603,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         } else {
             compute_es(Di, Bi);
             if constexpr (kEdge)
-                record(n);
+                record(n, kpl, pmask);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 R bsel;
@@ -651,7 +649,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
         // soft source
         if (kEdge && hasSrc && n <= rd->nsrc) {
-            const R g = (R)readlane_d(srcv, q);
+            const R g = gsrc;
             if constexpr (RING) {
                 if (smask) {
 #pragma unroll
@@ -671,7 +669,6 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int l0 = (int)(-x0 / C);
             if (lane == l0) {
                 if (abc == GFDTD_ABC_MUR1) {
-                    const R cL = (R)readlane_d(cLv, q);
                     Dn[0] = Di[1] + cL * (Dn[1] - Di[0]);
                 } else {
                     Dn[0] = (R)0;
@@ -684,7 +681,6 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int cr = (int)(r % C);
             const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
-            const R cR = (R)readlane_d(cRv, q);
             if (lane == lr) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
@@ -772,6 +768,18 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         int mEc = mE;                       // E shift at the current n - 1/2
         int mHc = mH;                       // H shift at the current n
         int nextx = G > 1 ? xk : nsub;      // step count of the next refresh
+        // Full step only: lane q holds the cell of probe q (bit q of pmask:
+        // this tile owns it), and per 64-step chunk lane j holds step j's
+        // source sample and end coefficients (FP64), so the steps read no
+        // memory.  Kept inside this loop: declared for the whole tile they
+        // raise the register allocation of the interior loop too.
+        int64_t kpl = -1;
+        uint64_t pmask = 0ull;
+        double srcv = 0.0, cLv = 0.0, cRv = 0.0;
+        if constexpr (kEdge) {
+            kpl = lane < nprobe ? rd->probes[lane] : (int64_t)-1;
+            pmask = __ballot(lane < nprobe && kpl >= own_lo && kpl < own_hi);
+        }
         for (int s0 = 0; s0 < nsub; s0 += kWave) {
             const int len = nsub - s0 < kWave ? nsub - s0 : kWave;
             const int sl = s0 + lane;
@@ -838,11 +846,15 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 // (D, B) and (D2, B2), so no copies between steps
                 int q = j;
                 for (; q + 1 <= stop; q += 2) {
-                    one_step(edge_tag, n0 + s0 + q, q, D, B, D2, B2);
-                    one_step(edge_tag, n0 + s0 + q + 1, q + 1, D2, B2, D, B);
+                    one_step(edge_tag, n0 + s0 + q, (R)readlane_d(srcv, q), (R)readlane_d(cLv, q),
+                             (R)readlane_d(cRv, q), kpl, pmask, D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q + 1, (R)readlane_d(srcv, q + 1),
+                             (R)readlane_d(cLv, q + 1), (R)readlane_d(cRv, q + 1), kpl, pmask,
+                             D2, B2, D, B);
                 }
                 if (q <= stop) {
-                    one_step(edge_tag, n0 + s0 + q, q, D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q, (R)readlane_d(srcv, q), (R)readlane_d(cLv, q),
+                             (R)readlane_d(cRv, q), kpl, pmask, D, B, D2, B2);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         D[c] = D2[c];
@@ -873,7 +885,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
 
         if (kEdge && last && ownsProbe) {   // the run ends in this block: E at N+1/2
             compute_es(D, B);
-            record(steps + 1);
+            record(steps + 1, kpl, pmask);
         }
     };
     if (touchL || touchR || hasSrc || ownsProbe)

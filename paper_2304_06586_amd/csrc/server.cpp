@@ -159,8 +159,9 @@ struct Request {
     size_t off = 0, bytes = 0;       // pool region
     size_t desc_off = 0;             // RunDesc, PrepDesc, DftDesc of the run
     int group = 0;                   // group_of(precision, kind, abc)
-    TileGeom geom;                   // one-wave tiles
-    int64_t ntiles = 0;
+    TileGeom geom;                   // one-wave tiles at its group's tiling
+    int64_t ntiles = 0;              // tiles at that tiling
+    int64_t ntiles_cap = 0;          // tiles at the narrowest tiling (bound)
     int64_t start_block = 0, end_block = 0;
     // pinned host block: inputs at admission, results at retirement
     void *host = nullptr;
@@ -193,7 +194,18 @@ struct Server {
     char *pool_base = nullptr;
     size_t pool_bytes = 0;
     int max_slots = 1;
-    int Cg[2] = {16, 8};             // cells per lane by precision
+    // Cells per lane, by tiling level and precision.  Level 0 is the
+    // throughput tiling; deeper levels use narrower lanes, so more waves
+    // share the same cells and each steps faster (a step's latency grows
+    // with the cells per lane).  The level is the first one at which the
+    // live runs fill kTargetTiles one-wave tiles (all tiles resident and
+    // several waves per SIMD), else the last: while the GPU is under-filled,
+    // narrower lanes cost nothing and shorten every request's latency.
+    static constexpr int kLevels = 3;
+    static constexpr int64_t kTargetTiles = 4096;    // 4 waves per SIMD
+    int Clev[kLevels][2] = {{16, 8}, {8, 4}, {4, 4}};
+    int level = 0;
+    int Cgrp[kGroups] = {};          // cells per lane of each group's tables
     int T = 32;
     Pool pool;
     size_t tables_bytes = 0;
@@ -206,7 +218,8 @@ struct Server {
     bool gdirty[kGroups] = {true, true, true, true, true, true, true, true};
     int cur[kGroups] = {};           // table buffer in use, per group
     size_t runs_off[2][kGroups], tiles_off[2][kGroups];
-    int ntiles[kGroups] = {};
+    int ntiles[kGroups] = {};        // tiles in each group's current table
+    int64_t cap_tiles[kGroups] = {}; // live tiles at the narrowest tiling
     int nwin[kGroups] = {};          // live requests with a time window
     // run-ahead tracking: events recorded on every group stream after each
     // run of block launches, with the global block count reached
@@ -304,8 +317,6 @@ struct Server {
         // cells per lane, FP64 8 (twice the registers per cell), 48 steps
         // per block; 12 cells and 32 steps served 7 % less, 8 and 24 a
         // further 17 % less.
-        Cg[0] = 16;
-        Cg[1] = 8;
         T = cfg->block_steps > 0 ? cfg->block_steps : 48;
         if (cfg->max_ahead < 0)
             return fail(GFDTD_E_INVALID, "max_ahead must be >= 0");
@@ -364,12 +375,18 @@ struct Server {
             return fail(GFDTD_E_NOMEM, "request needs %zu bytes, pool holds %zu",
                         rq->bytes, pool.size);
         rq->group = group_of(p->precision, p->kind, p->abc);
-        if (!tile_geometry(p->beta, Cg[p->precision], T, 1, 1, rq->geom))
+        if (!tile_geometry(p->beta, Clev[0][p->precision], T, 1, 1, rq->geom))
             return fail(GFDTD_E_INVALID, "block depth too large");
         rq->ntiles = (p->nz + rq->geom.own - 1) / rq->geom.own;
-        if (rq->ntiles > tile_cap)
+        rq->ntiles_cap = rq->ntiles;
+        for (int l = 1; l < kLevels; ++l) {
+            TileGeom g;
+            if (tile_geometry(p->beta, Clev[l][p->precision], T, 1, 1, g))
+                rq->ntiles_cap = std::max<int64_t>(rq->ntiles_cap, (p->nz + g.own - 1) / g.own);
+        }
+        if (rq->ntiles_cap > tile_cap)
             return fail(GFDTD_E_NOMEM, "request needs %lld tiles, tables hold %lld",
-                        (long long)rq->ntiles, (long long)tile_cap);
+                        (long long)rq->ntiles_cap, (long long)tile_cap);
         rq->id = next_id++;
         *id = rq->id;
         queue.push_back(rq->id);
@@ -383,7 +400,7 @@ struct Server {
         hipError_t e;
         while (!queue.empty() && (int)live.size() < max_slots) {
             Request *rq = reqs[queue.front()].get();
-            if (ntiles[rq->group] + rq->ntiles > tile_cap)
+            if (cap_tiles[rq->group] + rq->ntiles_cap > tile_cap)
                 break;
             size_t off;
             if (!pool.alloc(rq->bytes, off))
@@ -402,7 +419,7 @@ struct Server {
             rq->start_block = gblock;
             rq->end_block = gblock + (rq->r.steps + T - 1) / T - 1;
             live.push_back(rq->id);
-            ntiles[rq->group] += (int)rq->ntiles;
+            cap_tiles[rq->group] += rq->ntiles_cap;
             if (rq->r.p.flags & GFDTD_FLAG_TIME_WINDOW)
                 nwin[rq->group] += 1;
             gdirty[rq->group] = true;
@@ -497,16 +514,49 @@ struct Server {
 
     // Write a group's tables into its spare buffer (stream-ordered after
     // every launch that used it) and switch to it.
+    // Tiles of request rq at cells per lane C (false: no valid geometry).
+    bool tiles_at(const Request *rq, int C, TileGeom &g, int64_t &n) const
+    {
+        if (!tile_geometry(rq->r.p.beta, C, T, 1, 1, g))
+            return false;
+        n = (rq->r.p.nz + g.own - 1) / g.own;
+        return true;
+    }
+
+    // Tiling level for the current live set (see Clev).
+    int choose_level() const
+    {
+        for (int l = 0; l < kLevels; ++l) {
+            int64_t n = 0;
+            bool ok = true;
+            for (uint64_t id : live) {
+                const Request *rq = reqs.at(id).get();
+                TileGeom g;
+                int64_t k = 0;
+                ok = ok && tiles_at(rq, Clev[l][rq->r.p.precision], g, k);
+                n += k;
+            }
+            if (!ok)
+                return l > 0 ? l - 1 : 0;
+            if (n >= kTargetTiles || l == kLevels - 1)
+                return l;
+        }
+        return 0;
+    }
+
     gfdtd_status rebuild_tables(int g)
     {
         hipError_t e;
         const int nxt = cur[g] ^ 1;
         std::vector<RunDesc> rd;
         std::vector<TileRef> tl;
+        Cgrp[g] = Clev[level][group_precision(g)];
         for (uint64_t id : live) {
             Request *rq = reqs[id].get();
             if (rq->group != g)
                 continue;
+            if (!tiles_at(rq, Cgrp[g], rq->geom, rq->ntiles))
+                return fail(GFDTD_E_INVALID, "no tiling at %d cells per lane", Cgrp[g]);
             RunDesc d;
             PrepDesc pd;
             DftDesc dd;
@@ -592,7 +642,7 @@ struct Server {
                 released[g].push_back(ev);
         rq->state = RETIRING;
         pool.release(rq->off - tables_bytes, rq->bytes);
-        ntiles[rq->group] -= (int)rq->ntiles;
+        cap_tiles[rq->group] -= rq->ntiles_cap;
         if (rq->r.p.flags & GFDTD_FLAG_TIME_WINDOW)
             nwin[rq->group] -= 1;
         live.erase(std::find(live.begin(), live.end(), rq->id));
@@ -629,6 +679,17 @@ struct Server {
                 continue;
             if (live.empty() || left <= 0)
                 break;
+            bool changed = false;
+            for (int g = 0; g < kGroups; ++g)
+                changed = changed || gdirty[g];
+            if (changed) {
+                const int l = choose_level();
+                if (l != level) {
+                    level = l;
+                    for (int g = 0; g < kGroups; ++g)
+                        gdirty[g] = gdirty[g] || ntiles[g] > 0;
+                }
+            }
             for (int g = 0; g < kGroups; ++g)
                 if (gdirty[g] && (st = rebuild_tables(g)) != GFDTD_OK)
                     return st;
@@ -651,7 +712,7 @@ struct Server {
                         continue;
                     const int pr = group_precision(g);
                     for (int w = 0; w < (nwin[g] ? 2 : 1); ++w) {
-                        e = launch_tiles(pr, group_kind(g), group_ring(g), w == 1, Cg[pr], 1,
+                        e = launch_tiles(pr, group_kind(g), group_ring(g), w == 1, Cgrp[g], 1,
                                          reinterpret_cast<const RunDesc *>(pool_base + runs_off[cur[g]][g]),
                                          reinterpret_cast<const TileRef *>(pool_base + tiles_off[cur[g]][g]),
                                          gblock, T, ntiles[g], gs[g >> 1]);

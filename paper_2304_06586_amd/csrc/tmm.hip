@@ -186,6 +186,12 @@ gfdtd_status tmm_layout(const gfdtd_tmm_stack *stacks, int32_t nstacks,
 
 using namespace gfdtd;
 
+namespace {
+// device time of the calling thread's last k_tmm launch (HIP events on its
+// stream), for gfdtd_tmm_kernel_ms
+thread_local double g_tmm_kernel_ms = -1.0;
+}  // namespace
+
 extern "C" {
 
 gfdtd_status gfdtd_tmm_workspace_bytes(const gfdtd_tmm_stack *stacks, int32_t nstacks,
@@ -263,6 +269,21 @@ gfdtd_status gfdtd_tmm(const gfdtd_tmm_stack *stacks, int32_t nstacks,
                             hipMemcpyHostToDevice, stream)))
         return hip_fail(e, "upload stacks");
     const unsigned blocks = (unsigned)((nres + 255) / 256);
+    // events bracketing the kernel alone; destroyed on every return path
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a)
+                (void)hipEventDestroy(a);
+            if (b)
+                (void)hipEventDestroy(b);
+        }
+    } ev;
+    g_tmm_kernel_ms = -1.0;
+    if ((e = hipEventCreate(&ev.a)) || (e = hipEventCreate(&ev.b)) ||
+        (e = hipEventRecord(ev.a, stream)))
+        return hip_fail(e, "transfer-matrix timing events");
     hipLaunchKernelGGL(k_tmm, dim3(blocks), dim3(256), 0, stream,
                        reinterpret_cast<const TmmDesc *>(ws + L.desc),
                        reinterpret_cast<const double *>(ws + L.eps),
@@ -271,13 +292,27 @@ gfdtd_status gfdtd_tmm(const gfdtd_tmm_stack *stacks, int32_t nstacks,
                        reinterpret_cast<const double *>(ws + L.omegas), nstacks, nomega,
                        reinterpret_cast<double *>(ws + L.t),
                        reinterpret_cast<double *>(ws + L.g));
-    if ((e = hipGetLastError()))
+    if ((e = hipGetLastError()) || (e = hipEventRecord(ev.b, stream)))
         return hip_fail(e, "launch transfer-matrix kernel");
     if ((e = hipMemcpyAsync(t, ws + L.t, (size_t)nres * 16, hipMemcpyDeviceToHost, stream)) ||
         (e = hipMemcpyAsync(gamma, ws + L.g, (size_t)nres * 16, hipMemcpyDeviceToHost,
                             stream)) ||
         (e = hipStreamSynchronize(stream)))
         return hip_fail(e, "transfer-matrix results");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess)
+        g_tmm_kernel_ms = ms;
+    return GFDTD_OK;
+}
+
+gfdtd_status gfdtd_tmm_kernel_ms(double *ms)
+{
+    clear_error();
+    if (!ms)
+        return fail(GFDTD_E_INVALID, "ms is NULL");
+    if (g_tmm_kernel_ms < 0.0)
+        return fail(GFDTD_E_INVALID, "no transfer-matrix kernel has run on this thread");
+    *ms = g_tmm_kernel_ms;
     return GFDTD_OK;
 }
 

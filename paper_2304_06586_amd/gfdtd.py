@@ -161,6 +161,7 @@ EXPORTS = {
                                             C.c_int32, C.POINTER(C.c_size_t)]),
     "gfdtd_tmm": (C.c_int, [C.POINTER(gfdtd_tmm_stack), C.c_int32, _PD, C.c_int32,
                             C.c_void_p, C.c_size_t, C.c_void_p, _PD, _PD]),
+    "gfdtd_tmm_kernel_ms": (C.c_int, [C.POINTER(C.c_double)]),
 }
 
 
@@ -439,6 +440,14 @@ def gfdtd_tmm(stacks: Sequence, omegas, stream=None):
                          t.ctypes.data_as(_PD), g.ctypes.data_as(_PD)))
     del keep
     return t[..., 0] + 1j * t[..., 1], g[..., 0] + 1j * g[..., 1]
+
+
+def gfdtd_tmm_kernel_ms() -> float:
+    """Device time (ms) of the transfer-matrix kernel in this thread's last
+    gfdtd_tmm call."""
+    ms = C.c_double(0.0)
+    _check(load_library().gfdtd_tmm_kernel_ms(C.byref(ms)))
+    return ms.value
 
 
 class Batch:

@@ -73,3 +73,16 @@ def test_single_interface_and_slab_closed_forms(P, beta):
     for j, w in enumerate(omegas):
         ts, gs = A.slab(w, 1.0, 4.0, beta, 37.0)
         assert abs(abs(T[0, j]) - abs(ts)) < 1e-12 and abs(abs(G[0, j]) - abs(gs)) < 1e-12
+
+
+def test_kernel_time_is_reported(P):
+    """gfdtd_tmm_kernel_ms gives the device time of the kernel alone: after
+    a call it is positive and below the call's wall time."""
+    import time
+    stacks, omegas = W.tmm_crystals(5, 256, nomega=64)
+    t0 = time.perf_counter()
+    P.gfdtd_tmm(stacks, omegas)
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    k = P.gfdtd_tmm_kernel_ms()
+    print(f"transfer-matrix call {wall_ms:.3f} ms, kernel {k:.3f} ms")
+    assert 0.0 < k < wall_ms
