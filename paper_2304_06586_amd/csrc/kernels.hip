@@ -95,6 +95,15 @@ __device__ __forceinline__ double fmad(double a, double b, double c)
     return __builtin_fma(a, b, c);
 }
 
+// The same pointer in the global address space: loads and stores through
+// it are global (not flat) instructions, which count on the vector memory
+// counter only.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *glb(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Lane l's value of v, for a wave-uniform l (v_readlane, no LDS).
 __device__ __forceinline__ int readlane_i(int v, int l)
 {
@@ -214,7 +223,8 @@ __device__ __forceinline__ void shift_window(R (&a)[C])
 
 // a[idx] for a register array and a wave-uniform runtime idx, written as
 // a chain of selects with constant indices only (an indexed read would
-// force the array out of registers).
+// force the array out of registers; a flat select loop over the registers
+// is turned back into one by the compiler).
 template <typename R, int C, int I = C - 1>
 __device__ __forceinline__ R pick(const R (&a)[C], int idx)
 {
@@ -222,6 +232,21 @@ __device__ __forceinline__ R pick(const R (&a)[C], int idx)
         return a[0];
     else
         return idx == I ? a[I] : pick<R, C, I - 1>(a, idx);
+}
+
+// Register idx of lane l of a lane-distributed array, for a wave-uniform
+// idx and l: every register of lane l read into a scalar, then scalar
+// selects (no branches, and the array stays in registers).
+template <typename R, int C>
+__device__ __forceinline__ R pick_lane(const R (&a)[C], int idx, int l)
+{
+    R r = readlane_r(a[0], l);
+#pragma unroll
+    for (int c = 1; c < C; ++c) {
+        const R t = readlane_r(a[c], l);
+        r = (idx == c) ? t : r;
+    }
+    return r;
 }
 
 // ------------------------------------------------------------- the tile
@@ -243,6 +268,13 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                                           R *__restrict__ xbuf)
 {
     const int G = MW ? G_ : 1;          // one-wave tiles carry no refresh code
+    // The full step's single-cell updates (source, end nodes, probe reads)
+    // at a wave-uniform register: for narrow lanes as selects over the
+    // registers (no branches: a lone run is bound by the latency of a step),
+    // for wide lanes as branches to the one register (throughput tilings,
+    // where the full-step tiles share the SIMDs with the others and
+    // O(C) selects per step cost more than the branches).
+    constexpr bool kSelects = C <= 8;
     constexpr bool kMatter = (KIND == GFDTD_MATTER);
     const int lane = threadIdx.x & (kWave - 1);
 
@@ -300,11 +332,13 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
 
     const R *__restrict__ Dsrc = static_cast<const R *>(rd->D[par]);
     const R *__restrict__ Bsrc = static_cast<const R *>(rd->B[par]);
+    const auto Dsg = glb(Dsrc);        // the same, in the global address space
+    const auto Bsg = glb(Bsrc);
     R *__restrict__ Ddst = static_cast<R *>(rd->D[par ^ 1]);
     R *__restrict__ Bdst = static_cast<R *>(rd->B[par ^ 1]);
-    const R *__restrict__ cEp = static_cast<const R *>(rd->cE);
-    const R *__restrict__ cHp = static_cast<const R *>(rd->cH);
-    const R *__restrict__ gBp = static_cast<const R *>(rd->gB);
+    const auto cEp = glb(static_cast<const R *>(rd->cE));
+    const auto cHp = glb(static_cast<const R *>(rd->cH));
+    const auto gBp = glb(static_cast<const R *>(rd->gB));
 
     // On a ring every index is taken modulo nz: a window that crosses an
     // end (or a ring shorter than the window) loads cell by cell.
@@ -314,8 +348,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         int64_t i = kw;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            D[c] = Dsrc[i];
-            B[c] = Bsrc[i];
+            D[c] = Dsg[i];
+            B[c] = Bsg[i];
             i = ring_next(i, nz);
         }
     } else {
@@ -445,16 +479,15 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const R b0 = readlane_r(Bv[0], l0);
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                if (kb + c < 0)
-                    Bv[c] = b0;
+                Bv[c] = (kb + c < 0) ? b0 : Bv[c];
         }
         if (touchR) {
             const int64_t r = nz - 2 - x0;
-            const R bl = readlane_r(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
+            const R bl = kSelects ? pick_lane<R, C>(Bv, (int)(r % C), (int)(r / C))
+                                  : readlane_r(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                if (kb + c >= nz - 1)
-                    Bv[c] = bl;
+                Bv[c] = (kb + c >= nz - 1) ? bl : Bv[c];
         }
     };
     if (touchL || touchR)
@@ -528,21 +561,30 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     }
 
     // Physical E = E* + beta Bbar at the owned probes, for time n-1/2
-    // (E* = E~ / S); lane q of kpl holds the cell of probe q and bit q of
-    // pmask says this tile owns it.
-    auto record = [&](int64_t n, int64_t kpl, uint64_t pmask) __attribute__((always_inline)) {
-        if (n < 2 || !ownsProbe)
+    // (E* = E~ / S).  Lane q of the probe table describes probe q: plc =
+    // lane * C + register of its cell in this tile, prow = its trace row
+    // (the value for time n-1/2 goes to prow[n-2]); bit q of pmask says this
+    // tile owns it.
+    auto record = [&](int64_t n, int plc, double *prow, uint64_t pmask)
+                      __attribute__((always_inline)) {
+        if (n < 2)
             return;
         for (uint64_t m = pmask; m != 0ull; m &= m - 1ull) {
             const int q = (int)__builtin_ctzll(m);
-            const int64_t kp = readlane_i64(kpl, q);
-            const int lp = (int)((kp - x0) / C);
-            const int cp = (int)((kp - x0) % C);
-            const R e = pick<R, C>(Es, cp);
-            const R sm = pick<R, C>(sums, cp);
-            if (lane == lp)
-                rd->trace[(int64_t)q * steps + (n - 2)] =
-                    (double)e * invS64 + beta64 * (0.5 * (double)sm);
+            const int pc = readlane_i(plc, q);
+            double *row = reinterpret_cast<double *>(
+                readlane_i64(reinterpret_cast<int64_t>(prow), q));
+            if constexpr (kSelects) {
+                const R e = pick_lane<R, C>(Es, pc % C, pc / C);
+                const R sm = pick_lane<R, C>(sums, pc % C, pc / C);
+                // a wave-uniform value: every lane stores it to one address
+                glb(row)[n - 2] = (double)e * invS64 + beta64 * (0.5 * (double)sm);
+            } else {
+                const R e = pick<R, C>(Es, pc % C);
+                const R sm = pick<R, C>(sums, pc % C);
+                if (lane == pc / C)
+                    glb(row)[n - 2] = (double)e * invS64 + beta64 * (0.5 * (double)sm);
+            }
         }
     };
 
@@ -563,9 +605,10 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
 
     // One time step n with fixed coefficient windows, from (Di, Bi) to
     // (Dn, Bn).  The full step also takes the step's source sample gsrc and
-    // end coefficients cL, cR, and the probe cells (kpl, pmask as in record).
-    auto one_step = [&](auto edge_tag, int64_t n, R gsrc, R cL, R cR, int64_t kpl,
-                        uint64_t pmask,
+    // end coefficients cL, cR, and the probe table (plc, prow, pmask as in
+    // record).
+    auto one_step = [&](auto edge_tag, int64_t n, R gsrc, R cL, R cR, int plc,
+                        double *prow, uint64_t pmask,
                         const R (&Di)[C], const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
                         __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
@@ -579,9 +622,9 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // column b; E~ itself is formed only where a probe needs it.
         R P[C];
         if constexpr (!kMatter) {
-            if constexpr (kEdge) {
+            if (kEdge && pmask != 0ull) {
                 compute_es(Di, Bi);
-                record(n, kpl, pmask);
+                record(n, plc, prow, pmask);
             }
             if constexpr (!NEG) {
                 const R Bm1 = from_left(Bi[C - 1]);
@@ -602,8 +645,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         } else {
             compute_es(Di, Bi);
-            if constexpr (kEdge)
-                record(n, kpl, pmask);
+            if (kEdge && pmask != 0ull)
+                record(n, plc, prow, pmask);
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 R bsel;
@@ -657,6 +700,11 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                         if ((smask >> c) & 1u)
                             Dn[c] += g;
                 }
+            } else if (kSelects) {
+                const bool atS = lane == ls;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    Dn[c] = (atS && c == cs) ? Dn[c] + g : Dn[c];
             } else if (lane == ls) {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
@@ -667,13 +715,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // end nodes, at time n+1/2
         if (kEdge && touchL) {
             const int l0 = (int)(-x0 / C);
-            if (lane == l0) {
-                if (abc == GFDTD_ABC_MUR1) {
-                    Dn[0] = Di[1] + cL * (Dn[1] - Di[0]);
-                } else {
-                    Dn[0] = (R)0;
-                }
-            }
+            const R v = (abc == GFDTD_ABC_MUR1) ? Di[1] + cL * (Dn[1] - Di[0]) : (R)0;
+            Dn[0] = (lane == l0) ? v : Dn[0];
         }
         if (kEdge && touchR) {
             const int64_t r = nz - 1 - x0;
@@ -681,7 +724,18 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const int cr = (int)(r % C);
             const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
-            if (lane == lr) {
+            const bool atR = lane == lr;
+            if constexpr (kSelects) {
+                // only register cr of lane lr changes, so a later register's
+                // left neighbour is never one rewritten here
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const R po = (c >= 1) ? Di[c >= 1 ? c - 1 : 0] : dlo;
+                    const R pn = (c >= 1) ? Dn[c >= 1 ? c - 1 : 0] : dln;
+                    const R v = (abc == GFDTD_ABC_MUR1) ? po + cR * (pn - Di[c]) : (R)0;
+                    Dn[c] = (atR && c == cr) ? v : Dn[c];
+                }
+            } else if (atR) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     if (c == cr) {
@@ -773,12 +827,16 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // source sample and end coefficients (FP64), so the steps read no
         // memory.  Kept inside this loop: declared for the whole tile they
         // raise the register allocation of the interior loop too.
-        int64_t kpl = -1;
+        int plc = 0;
+        double *prow = nullptr;
         uint64_t pmask = 0ull;
         double srcv = 0.0, cLv = 0.0, cRv = 0.0;
         if constexpr (kEdge) {
-            kpl = lane < nprobe ? rd->probes[lane] : (int64_t)-1;
-            pmask = __ballot(lane < nprobe && kpl >= own_lo && kpl < own_hi);
+            const int64_t kpl = lane < nprobe ? glb(rd->probes)[lane] : (int64_t)-1;
+            const bool own = lane < nprobe && kpl >= own_lo && kpl < own_hi;
+            pmask = __ballot(own);
+            plc = own ? (int)(kpl - x0) : 0;
+            prow = rd->trace + (lane < nprobe ? (int64_t)lane * steps : 0);
         }
         for (int s0 = 0; s0 < nsub; s0 += kWave) {
             const int len = nsub - s0 < kWave ? nsub - s0 : kWave;
@@ -796,14 +854,14 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 // under the end nodes (the background one while a time
                 // window has the profile off)
                 const int64_t nl = n0 + sl;
-                srcv = (hasSrc && sl < nsub && nl <= rd->nsrc) ? rd->src[nl - 1] : 0.0;
+                srcv = (hasSrc && sl < nsub && nl <= rd->nsrc) ? glb(rd->src)[nl - 1] : 0.0;
                 if ((touchL || touchR) && abc == GFDTD_ABC_MUR1 && sl < nsub) {
                     const int mEl = profile_shift32(bS64, tn + 0.5);
                     const bool onl = !windowed || active(tn + 0.5);
                     if (touchL)
-                        cLv = onl ? rd->murL[clampi(-mEl, 0, nz - 1)] : rd->murB;
+                        cLv = onl ? glb(rd->murL)[clampi(-mEl, 0, nz - 1)] : rd->murB;
                     if (touchR)
-                        cRv = onl ? rd->murR[clampi(nz - 1 - mEl, 0, nz - 1)] : rd->murB;
+                        cRv = onl ? glb(rd->murR)[clampi(nz - 1 - mEl, 0, nz - 1)] : rd->murB;
                 }
             }
             // finite-duration modulation: bit j of hsw / esw = the H / E
@@ -847,14 +905,14 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 int q = j;
                 for (; q + 1 <= stop; q += 2) {
                     one_step(edge_tag, n0 + s0 + q, (R)readlane_d(srcv, q), (R)readlane_d(cLv, q),
-                             (R)readlane_d(cRv, q), kpl, pmask, D, B, D2, B2);
+                             (R)readlane_d(cRv, q), plc, prow, pmask, D, B, D2, B2);
                     one_step(edge_tag, n0 + s0 + q + 1, (R)readlane_d(srcv, q + 1),
-                             (R)readlane_d(cLv, q + 1), (R)readlane_d(cRv, q + 1), kpl, pmask,
-                             D2, B2, D, B);
+                             (R)readlane_d(cLv, q + 1), (R)readlane_d(cRv, q + 1), plc, prow,
+                             pmask, D2, B2, D, B);
                 }
                 if (q <= stop) {
                     one_step(edge_tag, n0 + s0 + q, (R)readlane_d(srcv, q), (R)readlane_d(cLv, q),
-                             (R)readlane_d(cRv, q), kpl, pmask, D, B, D2, B2);
+                             (R)readlane_d(cRv, q), plc, prow, pmask, D, B, D2, B2);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         D[c] = D2[c];
@@ -883,9 +941,9 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         }
 
-        if (kEdge && last && ownsProbe) {   // the run ends in this block: E at N+1/2
+        if (kEdge && last && pmask != 0ull) {   // the run ends in this block: E at N+1/2
             compute_es(D, B);
-            record(steps + 1, kpl, pmask);
+            record(steps + 1, plc, prow, pmask);
         }
     };
     if (touchL || touchR || hasSrc || ownsProbe)
@@ -899,20 +957,30 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     }
 }
 
-// Occupancy target: the refresh code of a multi-wave FP32 tile of a moving
-// modulation at 12 cells per lane would otherwise just exceed the 96
-// registers of 5 waves per SIMD.
+// Occupancy target: waves per SIMD the register allocation must allow
+// (512 registers per SIMD lane, at most 8 waves).  Each value is what the
+// tiling fits in without spilling; stated because the compiler, left to
+// itself, may give up a wave for one or two registers of the full-step loop
+// (FP64 at 12 cells per lane took 169 registers, 2 waves, instead of 168, 3).
 template <typename R, int C, int KIND, bool MW>
-constexpr int mw_waves()
+constexpr int occupancy_target()
 {
-    return (MW && sizeof(R) == 4 && C == 12 && KIND == GFDTD_MODULATION) ? 5 : 1;
+    if constexpr (sizeof(R) == 4) {
+        if constexpr (KIND == GFDTD_MODULATION)
+            return C == 4 ? 8 : C == 8 ? 7 : C == 12 ? 5 : 4;
+        return C == 4 ? 8 : C == 8 ? 5 : C == 12 ? 4 : 3;
+    } else {
+        if constexpr (KIND == GFDTD_MODULATION)
+            return C == 4 ? (MW ? 5 : 7) : C == 8 ? 4 : C == 12 ? 3 : 2;
+        return C == 4 ? 5 : C == 8 ? 3 : C == 12 ? 2 : 1;
+    }
 }
 
 // MW = false: kWavesPerGroup independent one-wave tiles per workgroup (one).
 // MW = true: one tile of G waves per workgroup (blockDim = 64 G).
 template <typename R, int C, int KIND, bool RING, bool WIN, bool MW>
 __global__ __launch_bounds__(kWave *(MW ? kMaxTileWaves : kWavesPerGroup))
-__attribute__((amdgpu_waves_per_eu(mw_waves<R, C, KIND, MW>()))) void k_tiles(
+__attribute__((amdgpu_waves_per_eu(occupancy_target<R, C, KIND, MW>()))) void k_tiles(
     const RunDesc *__restrict__ runs, const TileRef *__restrict__ tiles,
     int64_t block, int T, int ntiles, int G)
 {
