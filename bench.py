@@ -9,19 +9,35 @@ timed region.  `value` is total cell-updates (sum over runs of nz * steps)
 per second of the timed passes.
 
 Printed beside it, in the same JSON line:
-  plain       -- the plain single-run form: the 65536-cell moving slab,
-                 131072 steps, FP32 and FP64, one run per pass;
-  error       -- relative L2 error against the FP64 oracle on a seeded
-                 sample of the same workload;
-  roofline    -- the stepping kernel (k_tiles) against the chip's vector
-                 ALU peak, timed with HIP events on the library's stream;
-  cpu_baseline-- the oracle on the host cores on a bounded sample.
+  roofline     -- the stepping kernel (k_tiles) of the timed pass against
+                  the chip's vector-ALU peak, timed with HIP events on the
+                  library's stream;
+  batched_f64  -- the same batch in FP64, with its kernel roofline;
+  serving      -- the continuous-batching server on the serving mix (grid
+                  lengths log-uniform in [1e3, 1e6], 2 GiB pool): saturated
+                  rate, and at each offered load the throughput, p50/p99
+                  latency, mean queueing delay, rejections and (at the
+                  lowest load) each request's slowdown against its alone
+                  time;
+  plain        -- the plain single-run form of the interface (2000 cells x
+                  4000 steps), slab (65536 x 131072) and moving-matter
+                  gradient (2^20 x 2^18) workloads, FP32 and FP64: rate,
+                  kernel roofline, error against the FP64 oracle (the
+                  gradient on its 2^14 x 2^12 downscaled copy, and FP32
+                  against FP64 at full size) and the oracle's own rate on
+                  the host;
+  tmm_sweep    -- the batched transfer-matrix evaluator: call and kernel
+                  time;
+  error        -- the FP32 batch's probe spectra against the oracle on a
+                  sample of its runs at their full step counts;
+  cpu_baseline -- the oracle on the host cores on that sample.
 """
 import argparse
 import json
 import math
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -49,11 +65,14 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_tiles_f32_crystals4096_hbm_counters.txt")
+COUNTERS = {
+    W.F32: os.path.join(ROOT, "profiles", "k_tiles_f32_crystals4096_hbm_counters.txt"),
+    W.F64: os.path.join(ROOT, "profiles", "k_tiles_f64_crystals4096_hbm_counters.txt"),
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic_per_update(C, T):
+def measured_traffic_per_update(C, T, precision=W.F32):
     """HBM bytes per cell-update of k_tiles from the committed rocprofv3
     FETCH_SIZE/WRITE_SIZE counters (scaled by a plain copy), or None when
     the kernel source has changed since they were taken or they were taken
@@ -61,7 +80,7 @@ def measured_traffic_per_update(C, T):
     import hashlib
     try:
         kv = {}
-        for line in open(COUNTERS):
+        for line in open(COUNTERS[precision]):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
@@ -75,10 +94,53 @@ def measured_traffic_per_update(C, T):
         return None
 
 
-def gpu_pass_rate(P, problems, passes, warmup, tune=True, **exec_kw):
+def kernel_roofline(st, updates, precision):
+    """k_tiles of the last pass against the vector-ALU peak, from the
+    library's HIP events around the pass's stepping launches."""
+    step_s = st["step_ms"] / 1e3
+    launches = max(1, int(st["launches"]))
+    avg_launch_ms = st["step_ms"] / launches
+    k_rate = updates / step_s if step_s > 0 else 0.0
+    achieved = k_rate * FLOPS_PER_UPDATE / 1e12
+    per_update = measured_traffic_per_update(int(st["cells_per_lane"]),
+                                             int(st["block_steps"]), precision)
+    upd_per_launch = updates / launches
+    traffic = per_update * upd_per_launch if per_update is not None else None
+    hbm_equiv = k_rate * BYTES_PER_UPDATE[precision] / 1e9
+    return {
+        "kernel": "k_tiles",
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": round(ALU_PEAK_TFLOPS, 1),
+        "unit": "TFLOP/s",
+        "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                        "copy-calibrated)",
+        "measured_hbm_GBs": (round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
+                             if traffic is not None and avg_launch_ms > 0 else None),
+        "algorithmic_bytes_per_launch": upd_per_launch * BYTES_PER_UPDATE[precision],
+        "flops_per_update": FLOPS_PER_UPDATE,
+        "kernel_cell_updates_per_s": k_rate,
+        "launches_per_pass": launches,
+        "avg_launch_ms": round(avg_launch_ms, 4),
+        "cells_per_lane": int(st["cells_per_lane"]),
+        "block_steps": int(st["block_steps"]),
+        "tile_waves": int(st["tile_waves"]),
+        "graph": int(st["graph"]),
+        "single_step_hbm_equiv_GBs": round(hbm_equiv, 1),
+        "single_step_hbm_frac": round(hbm_equiv / HBM_PEAK_GBS, 3),
+    }
+
+
+def gpu_pass_rate(P, problems, passes, warmup, tune=True, collect=False,
+                  record_trace=False, **exec_kw):
+    """Seconds for `passes` passes of a batch (after autotuning and
+    warm-up, both outside the timed region), its stats, and its results
+    when `collect`."""
     import torch
-    with P.Batch(problems, record_trace=False, fields=False, **exec_kw) as b:
-        if tune:                      # outside the timed region
+    with P.Batch(problems, record_trace=record_trace, fields=False, **exec_kw) as b:
+        if tune:
             b.autotune(trial_blocks=4)
         for _ in range(warmup):
             b.run()
@@ -89,34 +151,44 @@ def gpu_pass_rate(P, problems, passes, warmup, tune=True, **exec_kw):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = b.stats()
-    return dt, st
+        out = b.collect() if collect else None
+    return dt, st, out
 
+
+def rel(a, b):
+    den = np.linalg.norm(np.ravel(b))
+    num = np.linalg.norm(np.ravel(a) - np.ravel(b))
+    return float(num / den) if den > 0 else float(num)
+
+
+# ------------------------------------------------------------------ serving
 
 def serve(P, stream, pool_bytes, max_slots, blocks_per_call=64, closed=False):
     """Drive the continuous-batching server with a request stream of
     (arrival time, problem).  closed=True submits everything at t = 0.
     Returns a dict: the seconds from the first arrival to the last
-    completion, per-request latencies (s), total cell-updates, the
-    (completion time, cell-updates) of every request, rejections, and the
-    mean time a request waits for admission: by Little's law the time
-    integral of the server's queue length divided by the requests that
-    entered it."""
-    lat = []
+    completion, each request's latency in stream order (s, None if
+    rejected), total cell-updates, the (completion time, cell-updates) of
+    every request, rejections, and the mean time a request waits for
+    admission: by Little's law the time integral of the server's queue
+    length divided by the requests that entered it."""
+    n = len(stream)
+    lat = [None] * n
     done = []
     updates = 0
     rejected = 0
     queue_area = 0.0
-    last_q, last_t = 0, 0.0
+    live_area = 0.0
+    last_q, last_live, last_t = 0, 0, 0.0
     accepted = 0
+    finished = 0
     with P.Server(pool_bytes=pool_bytes, max_slots=max_slots) as srv:
         pending = {}
         i = 0
-        n = len(stream)
         t0 = time.perf_counter()
-        while len(lat) + rejected < n:
+        while finished + rejected < n:
             now = time.perf_counter() - t0
             while i < n and (closed or stream[i][0] <= now):
-                arr = 0.0 if closed else stream[i][0]
                 prob = stream[i][1]
                 try:
                     rid = srv.submit(prob)
@@ -124,29 +196,47 @@ def serve(P, stream, pool_bytes, max_slots, blocks_per_call=64, closed=False):
                     rejected += 1
                     i += 1
                     continue
-                pending[rid] = (arr, prob.nz * prob.steps)
+                pending[rid] = (i, 0.0 if closed else stream[i][0], prob.nz * prob.steps)
                 updates += prob.nz * prob.steps
                 accepted += 1
                 i += 1
             if pending:
                 now = time.perf_counter() - t0
                 queue_area += last_q * (now - last_t)
-                _, last_q = srv.progress(max_blocks=blocks_per_call)
+                live_area += last_live * (now - last_t)
+                last_live, last_q = srv.progress(max_blocks=blocks_per_call)
                 last_t = now
                 for rid in list(pending):
                     if srv.ready(rid):
                         now = time.perf_counter() - t0
                         r = srv.poll(rid)
                         assert r["status"] == 0
-                        arr, work = pending.pop(rid)
-                        lat.append(now - arr)
+                        k, arr, work = pending.pop(rid)
+                        lat[k] = now - arr
                         done.append((now, work))
+                        finished += 1
             elif i < n:
                 time.sleep(max(0.0, min(0.01, stream[i][0] - now)))
         total = time.perf_counter() - t0
     return {"total_s": total, "latency_s": lat, "updates": updates,
             "done": sorted(done), "rejected": rejected,
-            "queue_wait_mean_s": queue_area / max(1, accepted)}
+            "queue_wait_mean_s": queue_area / max(1, accepted),
+            "live_mean": live_area / max(total, 1e-9),
+            "queue_mean": queue_area / max(total, 1e-9)}
+
+
+def alone_latencies(P, problems, pool_bytes, max_slots, blocks_per_call=64):
+    """Latency of each request served alone, by the same server and loop."""
+    out = []
+    with P.Server(pool_bytes=pool_bytes, max_slots=max_slots) as srv:
+        for p in problems:
+            t0 = time.perf_counter()
+            rid = srv.submit(p)
+            while not srv.ready(rid):
+                srv.progress(max_blocks=blocks_per_call)
+            srv.poll(rid)
+            out.append(time.perf_counter() - t0)
+    return out
 
 
 def saturated_rate(done, lo=0.1, hi=0.7):
@@ -156,21 +246,102 @@ def saturated_rate(done, lo=0.1, hi=0.7):
     alone, are left out)."""
     t = np.array([d[0] for d in done])
     w = np.cumsum([d[1] for d in done])
-    W = w[-1]
-    i0 = int(np.searchsorted(w, lo * W))
-    i1 = int(np.searchsorted(w, hi * W))
+    W_ = w[-1]
+    i0 = int(np.searchsorted(w, lo * W_))
+    i1 = int(np.searchsorted(w, hi * W_))
     if i1 <= i0 or t[i1] <= t[i0]:
-        return W / t[-1]
+        return W_ / t[-1]
     return float((w[i1] - w[i0]) / (t[i1] - t[i0]))
 
 
-def cpu_baseline(sample, threads):
-    import oracle
-    t0 = time.perf_counter()
-    outs = oracle.solve_many(sample, threads=threads, fields=False)
-    dt = time.perf_counter() - t0
-    upd = sum(p.nz * p.steps for p in sample)
-    return upd / dt, dt, outs
+def serving_leg(P, args):
+    pool = int(args.serve_budget_gib * (1 << 30))
+    slots = args.serve_slots
+    sat_stream = W.serving_stream(args.seed, args.serve_sat_requests, 1.0,
+                                  nz_hi=args.serve_nz_hi)
+    sat = serve(P, sat_stream, pool, slots, closed=True)
+    cap = saturated_rate(sat["done"])
+    mean_work = sat["updates"] / len(sat_stream)
+    cap_rps = cap / mean_work
+    log(f"serving: saturated {cap:.4g} cell-updates/s ({cap_rps:.2f} req/s)")
+    loads = []
+    for li, frac in enumerate([float(x) for x in args.serve_loads.split(",") if x]):
+        rate = frac * cap_rps
+        n = max(args.serve_min_requests, int(round(rate * args.serve_seconds)))
+        stream = W.serving_stream(args.seed + 1 + li, n, rate, nz_hi=args.serve_nz_hi)
+        res = serve(P, stream, pool, slots)
+        lat = np.array([x for x in res["latency_s"] if x is not None])
+        entry = {
+            "offered_fraction": frac,
+            "offered_requests_per_s": round(rate, 3),
+            "requests": n,
+            "offered_seconds": round(stream[-1][0], 2),
+            "cell_updates_per_s": res["updates"] / res["total_s"],
+            "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+            "queue_wait_mean_ms": res["queue_wait_mean_s"] * 1e3,
+            "queued_mean": round(res["queue_mean"], 2),
+            "live_mean": round(res["live_mean"], 2),
+            "rejected": res["rejected"],
+        }
+        if li == 0 and args.serve_alone:
+            # each request of the lightest load served alone, same server
+            idx = [k for k, x in enumerate(res["latency_s"]) if x is not None]
+            alone = alone_latencies(P, [stream[k][1] for k in idx], pool, slots)
+            slow = np.array([res["latency_s"][k] / a for k, a in zip(idx, alone)])
+            entry["slowdown_vs_alone"] = {
+                "p50": float(np.percentile(slow, 50)),
+                "p99": float(np.percentile(slow, 99)),
+                "max": float(np.max(slow)),
+                "requests": len(slow),
+                "note": "latency in the mix / latency of the same request served "
+                        "alone by the same server",
+            }
+        loads.append(entry)
+        log(f"serving at {frac:.2f} of capacity ({rate:.2f} req/s, {n} requests): "
+            f"p50 {entry['p50_latency_ms']:.1f} ms p99 {entry['p99_latency_ms']:.1f} ms, "
+            f"queueing {entry['queue_wait_mean_ms']:.1f} ms, live {entry['live_mean']}, "
+            f"queued {entry['queued_mean']}"
+            + (f", slowdown p99 {entry['slowdown_vs_alone']['p99']:.2f}"
+               if "slowdown_vs_alone" in entry else ""))
+    return {
+        "saturated_cell_updates_per_s": cap,
+        "saturated_requests_per_s": cap_rps,
+        "saturated_note": "slope of completed work vs time between 10 % and "
+                          "70 % of the total, all requests submitted at t = 0",
+        "makespan_cell_updates_per_s": sat["updates"] / sat["total_s"],
+        "saturated_requests": len(sat_stream),
+        "loads": loads,
+        "mix": f"interface/slab/crystal/gradient, nz log-uniform in "
+               f"[1e3, {args.serve_nz_hi:.0e}], steps U[2,4] nz, "
+               "FP32 or FP64 with p = 1/2, Poisson arrivals",
+        "budget_GiB": args.serve_budget_gib,
+        "max_slots": slots,
+    }
+
+
+# ----------------------------------------------------------- oracle (host)
+
+class OracleJobs(threading.Thread):
+    """The oracle on a list of (name, problem) in one host thread (the C
+    stepper releases the interpreter lock), timing each run."""
+
+    def __init__(self, jobs):
+        super().__init__(daemon=True)
+        self.jobs = jobs
+        self.results = {}
+        self.error = None
+
+    def run(self):
+        try:
+            import oracle
+            for name, p in self.jobs:
+                t0 = time.perf_counter()
+                out = oracle.solve(p, fields=False)
+                dt = time.perf_counter() - t0
+                self.results[name] = (out, dt, p.nz * p.steps)
+        except Exception as e:          # reported in the line, not raised
+            self.error = repr(e)
 
 
 def main():
@@ -185,19 +356,25 @@ def main():
     ap.add_argument("--block-steps", type=int, default=0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample-runs", type=int, default=384)
-    ap.add_argument("--cpu-sample-steps", type=int, default=6000)
+    ap.add_argument("--cpu-sample-updates", type=float, default=6e10,
+                    help="cell-updates of the oracle sample of the batch (runs at "
+                         "full length, in batch order, each at most 4e9)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tiling instead of autotuning it")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-tmm", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9,1.1",
                     help="offered loads as fractions of the saturated request "
-                         "rate, comma separated")
-    ap.add_argument("--serve-nz-hi", type=float, default=1e5)
-    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+                         "rate, comma separated (the first also gets alone times)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="seconds of arrivals per offered load")
+    ap.add_argument("--serve-min-requests", type=int, default=24)
+    ap.add_argument("--serve-sat-requests", type=int, default=160)
+    ap.add_argument("--serve-nz-hi", type=float, default=1e6)
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--no-serve-alone", dest="serve_alone", action="store_false")
     ap.add_argument("--steps-cap", type=int, default=0, metavar="N",
                     help="cap every run at N steps: a shorter workload with the "
                          "same runs, tiles and launch shape, for counter "
@@ -240,120 +417,97 @@ def main():
         probs = [q.replace(steps=min(q.steps, args.steps_cap)) for q in probs]
     updates = float(sum(p.nz * p.steps for p in probs))
     log(f"cell-updates per pass: {updates:.4g}")
-    dt, st = gpu_pass_rate(P, probs, args.steps, args.warmup, **exec_kw)
+    dt, st, batch_out = gpu_pass_rate(P, probs, args.steps, args.warmup,
+                                      collect=not args.no_cpu, **exec_kw)
     value = updates * args.steps / dt
     ms_per_step = dt * 1e3 / args.steps
     log(f"batched: {value:.4g} cell-updates/s, {ms_per_step:.1f} ms per pass")
-
-    # roofline of the stepping kernel from the library's HIP events (last pass)
-    step_s = st["step_ms"] / 1e3
-    avg_launch_ms = st["step_ms"] / max(1, st["launches"])
-    k_rate = updates / step_s if step_s > 0 else 0.0
-    achieved_tflops = k_rate * FLOPS_PER_UPDATE / 1e12
-    hbm_equiv = k_rate * BYTES_PER_UPDATE[prec] / 1e9
-    per_update = (measured_traffic_per_update(int(st["cells_per_lane"]),
-                                              int(st["block_steps"]))
-                  if prec == W.F32 else None)
-    upd_per_launch = updates / max(1, st["launches"])
-    traffic = per_update * upd_per_launch if per_update is not None else None
-    roofline = {
-        "kernel": "k_tiles",
-        "bound": "alu",
-        "achieved": round(achieved_tflops, 3),
-        "peak": round(ALU_PEAK_TFLOPS, 1),
-        "unit": "TFLOP/s",
-        "frac": round(achieved_tflops / ALU_PEAK_TFLOPS, 4),
-        "traffic": traffic,
-        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                        "copy-calibrated)",
-        "measured_hbm_GBs": (round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
-                             if traffic is not None and avg_launch_ms > 0 else None),
-        "algorithmic_bytes_per_launch": upd_per_launch * BYTES_PER_UPDATE[prec],
-        "flops_per_update": FLOPS_PER_UPDATE,
-        "launches_per_pass": int(st["launches"]),
-        "avg_launch_ms": round(avg_launch_ms, 4),
-        "cells_per_lane": int(st["cells_per_lane"]),
-        "block_steps": int(st["block_steps"]),
-        "single_step_hbm_equiv_GBs": round(hbm_equiv, 1),
-        "single_step_hbm_frac": round(hbm_equiv / HBM_PEAK_GBS, 3),
-    }
+    roofline = kernel_roofline(st, updates, prec)
 
     # --------------------------------------------------- batched, other dtype
     batched_f64 = None
     if not args.no_f64 and prec == W.F32 and not args.steps_cap:
         probs64 = [q.replace(precision=W.F64) for q in probs]
-        dt64, st64 = gpu_pass_rate(P, probs64, 1, 1, **exec_kw)
+        dt64, st64, _ = gpu_pass_rate(P, probs64, 1, 1, **exec_kw)
         batched_f64 = {"value": updates / dt64, "ms": dt64 * 1e3,
-                       "cells_per_lane": int(st64["cells_per_lane"]),
-                       "block_steps": int(st64["block_steps"]),
+                       "roofline": kernel_roofline(st64, updates, W.F64),
                        "hbm_equiv_frac": round(updates / dt64 * 32 / 8e12, 3)}
         log(f"batched f64: {batched_f64['value']:.4g} cell-updates/s")
         del probs64
 
+    # ---------------------------------- oracle of the plain configs, host thread
+    plain_defs = [
+        ("interface", lambda pr: W.interface_run(args.seed, precision=pr)),
+        ("slab", lambda pr: W.slab_run(args.seed, precision=pr)),
+        ("gradient", lambda pr: W.gradient_run(args.seed, precision=pr)),
+    ]
+    oracle_jobs = None
+    if not args.no_plain and not args.no_cpu:
+        oracle_jobs = OracleJobs([
+            ("interface", W.interface_run(args.seed, precision=W.F64)),
+            ("gradient_downscaled", W.gradient_run(args.seed, precision=W.F64,
+                                                   downscaled=True)),
+            ("slab", W.slab_run(args.seed, precision=W.F64)),
+        ])
+        oracle_jobs.start()         # overlaps the serving leg on one host core
+
     # ---------------------------------------------------------------- served
     serving = None
     if not args.no_serve:
-        pool = int(args.serve_budget_gb * (1 << 30))
-        stream = W.serving_stream(args.seed, args.serve_requests, 1.0,
-                                  nz_hi=args.serve_nz_hi)
-        sat = serve(P, stream, pool, 512, closed=True)
-        cap = saturated_rate(sat["done"])
-        mean_work = sat["updates"] / len(stream)
-        cap_rps = cap / mean_work
-        loads = []
-        for frac in [float(x) for x in args.serve_loads.split(",") if x]:
-            rate = frac * cap_rps
-            st = W.serving_stream(args.seed + 1, args.serve_requests, rate,
-                                  nz_hi=args.serve_nz_hi)
-            res = serve(P, st, pool, 512)
-            lat = np.array(res["latency_s"])
-            loads.append({
-                "offered_fraction": frac,
-                "offered_requests_per_s": round(rate, 2),
-                "cell_updates_per_s": res["updates"] / res["total_s"],
-                "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
-                "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
-                "queue_wait_mean_ms": res["queue_wait_mean_s"] * 1e3,
-                "rejected": res["rejected"],
-            })
-            log(f"serving at {frac:.2f} of capacity ({rate:.1f} req/s): "
-                f"p50 {loads[-1]['p50_latency_ms']:.1f} ms p99 "
-                f"{loads[-1]['p99_latency_ms']:.1f} ms, mean queueing "
-                f"{loads[-1]['queue_wait_mean_ms']:.1f} ms")
-        serving = {
-            "saturated_cell_updates_per_s": cap,
-            "saturated_requests_per_s": cap_rps,
-            "saturated_note": "slope of completed work vs time between 10 % and "
-                              "70 % of the total, all requests submitted at t = 0",
-            "makespan_cell_updates_per_s": sat["updates"] / sat["total_s"],
-            "loads": loads,
-            "requests": len(stream),
-            "mix": f"interface/slab/crystal/gradient, nz log-uniform in "
-                   f"[1e3, {args.serve_nz_hi:.0e}], steps U[2,4] nz, "
-                   "FP32 or FP64 with p = 1/2, Poisson arrivals",
-            "budget_GB": args.serve_budget_gb,
-        }
-        log(f"serving: saturated {cap:.4g} cell-updates/s ({cap_rps:.1f} req/s)")
+        serving = serving_leg(P, args)
 
     # ------------------------------------------------------------------ plain
     plain = None
     if not args.no_plain:
         plain = {}
-        for name, maker in (("interface", lambda pr: W.interface_run(args.seed, precision=pr)),
-                            ("slab", lambda pr: W.slab_run(args.seed, precision=pr)),
-                            ("gradient", lambda pr: W.gradient_run(args.seed,
-                                                                  precision=pr))):
+        gpu_out = {}
+        for name, maker in plain_defs:
             for pname, pr in (("f32", W.F32), ("f64", W.F64)):
                 p = maker(pr)
-                pdt, pst = gpu_pass_rate(P, [p], 1, 1, tune=not args.no_tune)
-                key = f"{name}_{pname}"
-                plain[key] = {"value": p.nz * p.steps / pdt, "ms": pdt * 1e3,
-                              "nz": p.nz, "steps": p.steps,
-                              "cells_per_lane": int(pst["cells_per_lane"]),
-                              "block_steps": int(pst["block_steps"]),
-                              "graph": int(pst["graph"])}
-                log(f"plain {key}: {plain[key]['value']:.4g} cell-updates/s "
-                    f"(C={pst['cells_per_lane']}, T={pst['block_steps']})")
+                pdt, pst, pout = gpu_pass_rate(P, [p], 1, 1, tune=not args.no_tune,
+                                               collect=True, record_trace=True)
+                gpu_out[(name, pname)] = pout[0]
+                plain[f"{name}_{pname}"] = {
+                    "value": p.nz * p.steps / pdt, "ms": pdt * 1e3,
+                    "nz": p.nz, "steps": p.steps,
+                    "roofline": kernel_roofline(pst, float(p.nz * p.steps), pr)}
+                log(f"plain {name}_{pname}: {plain[f'{name}_{pname}']['value']:.4g} "
+                    f"cell-updates/s, {pdt * 1e3:.2f} ms (C={pst['cells_per_lane']}, "
+                    f"T={pst['block_steps']})")
+        # the gradient's downscaled copy, against the oracle
+        for pname, pr in (("f32", W.F32), ("f64", W.F64)):
+            q = W.gradient_run(args.seed, precision=pr, downscaled=True)
+            gpu_out[("gradient_downscaled", pname)] = P.gfdtd_solve(q, fields=False)
+        # FP32 against FP64 at full gradient size (probe spectra and traces)
+        g32, g64 = gpu_out[("gradient", "f32")], gpu_out[("gradient", "f64")]
+        plain["gradient_f32"]["error_vs_gpu_f64"] = {
+            "dft_rel_l2": rel(g32["dft"], g64["dft"]),
+            "trace_rel_l2": rel(g32["trace"], g64["trace"])}
+        if oracle_jobs is not None:
+            oracle_jobs.join()
+            if oracle_jobs.error:
+                plain["oracle_error"] = oracle_jobs.error
+            for oname, key in (("interface", "interface"), ("slab", "slab"),
+                               ("gradient_downscaled", "gradient")):
+                if oname not in oracle_jobs.results:
+                    continue
+                ref, odt, oupd = oracle_jobs.results[oname]
+                for pname in ("f32", "f64"):
+                    g = gpu_out[(oname, pname)]
+                    err = {"trace_rel_l2": rel(g["trace"], ref["trace"]),
+                           "dft_rel_l2": rel(g["dft"], ref["dft"])}
+                    if oname == "gradient_downscaled":
+                        plain[f"{key}_{pname}"]["error_vs_oracle_downscaled"] = err
+                    else:
+                        plain[f"{key}_{pname}"]["error_vs_oracle"] = err
+                plain[f"{key}_f64"]["oracle"] = {
+                    "value": oupd / odt, "unit": "cell-updates/s", "cores": 1,
+                    "seconds": round(odt, 2),
+                    "sample": ("full run" if oname != "gradient_downscaled" else
+                               "the 2^14-cell, 2^12-step downscaled copy")}
+            log("plain errors vs oracle: " + ", ".join(
+                f"{k}: {v.get('error_vs_oracle', v.get('error_vs_oracle_downscaled', {})).get('trace_rel_l2', float('nan')):.2e}"
+                for k, v in plain.items() if isinstance(v, dict) and "value" in v))
 
     # ------------------------------------------- transfer-matrix sweep (GPU)
     tmm = None
@@ -362,19 +516,22 @@ def main():
         layers = sum(len(s.eps) for s in stacks)
         P.gfdtd_tmm(stacks[:8], omegas[:8])               # warm-up
         torch.cuda.synchronize()
-        dt = float("inf")
+        dt_call, dt_kernel = float("inf"), float("inf")
         for _ in range(3):                                 # best of three calls
             t0 = time.perf_counter()
-            Tg, Gg = P.gfdtd_tmm(stacks, omegas)
-            dt = min(dt, time.perf_counter() - t0)
+            P.gfdtd_tmm(stacks, omegas)
+            dt_call = min(dt_call, time.perf_counter() - t0)
+            dt_kernel = min(dt_kernel, P.gfdtd_tmm_kernel_ms() / 1e3)
         evals = len(stacks) * len(omegas)
-        tmm = {"stack_frequency_evals_per_s": evals / dt,
-               "layer_evals_per_s": layers * len(omegas) / dt,
-               "ms": dt * 1e3, "stacks": len(stacks), "frequencies": len(omegas),
-               "layers": layers,
-               "note": "one synchronous gfdtd_tmm call (best of three), host packing, "
-                       "host-to-device upload of the stacks and result copies "
-                       "included; FP64"}
+        tmm = {"stack_frequency_evals_per_s": evals / dt_call,
+               "kernel_stack_frequency_evals_per_s": evals / dt_kernel,
+               "layer_evals_per_s": layers * len(omegas) / dt_call,
+               "kernel_layer_evals_per_s": layers * len(omegas) / dt_kernel,
+               "call_ms": dt_call * 1e3, "kernel_ms": dt_kernel * 1e3,
+               "stacks": len(stacks), "frequencies": len(omegas), "layers": layers,
+               "note": "best of three synchronous gfdtd_tmm calls; call_ms includes "
+                       "host packing, host-to-device upload and result copies, "
+                       "kernel_ms is k_tmm alone (HIP events); FP64"}
         if not args.no_cpu:
             from oracle import analytic as A
             sub = stacks[:4]
@@ -385,38 +542,42 @@ def main():
                     A.transfer_matrix(w, list(s.eps), list(s.widths), s.beta)
             cdt = time.perf_counter() - c0
             tmm["cpu_oracle_stack_frequency_evals_per_s"] = len(sub) * len(om) / cdt
-        log(f"transfer-matrix sweep: {tmm['stack_frequency_evals_per_s']:.4g} "
-            f"(stack, omega) evaluations/s, {tmm['layer_evals_per_s']:.4g} layers/s")
+        log(f"transfer-matrix sweep: call {dt_call * 1e3:.2f} ms, kernel "
+            f"{dt_kernel * 1e3:.3f} ms")
 
-    # ---------------------------------------- error and CPU baseline (sample)
-    sample = [q.replace(steps=min(q.steps, args.cpu_sample_steps))
-              for q in W.crystal_runs(args.seed, count=args.cpu_sample_runs,
-                                      precision=prec)]
+    # ------------------- error and CPU baseline on a sample of the batch
     error = None
     cpu = None
     if not args.no_cpu:
+        import oracle
+        # runs of the batch at their full step counts, in batch order, each
+        # at most 4e9 cell-updates (one host thread per run)
+        sample_idx, acc = [], 0.0
+        for k, q in enumerate(probs):
+            if q.nz * q.steps <= 4e9:
+                sample_idx.append(k)
+                acc += q.nz * q.steps
+                if acc >= args.cpu_sample_updates:
+                    break
+        sample = [probs[k].replace(precision=W.F64) for k in sample_idx]
         threads = min(16, os.cpu_count() or 1)
-        log(f"oracle on {len(sample)} runs x <= {args.cpu_sample_steps} steps, "
+        log(f"oracle on {len(sample)} runs at full length ({acc:.3g} cell-updates), "
             f"{threads} threads")
-        rate, cdt, ref = cpu_baseline(sample, threads)
-        got = P.gfdtd_solve_batch(sample, fields=False)
-        errs = []
-        for g, r in zip(got, ref):
-            num = np.linalg.norm(g["trace"] - r["trace"])
-            den = np.linalg.norm(r["trace"])
-            errs.append(num / den if den > 0 else num)
-        error = {"trace_rel_l2_max": float(max(errs)),
-                 "trace_rel_l2_median": float(np.median(errs)),
-                 "vs": "FP64 oracle", "sample": f"first {len(sample)} runs, "
-                 f"steps capped at {args.cpu_sample_steps}"}
-        cpu = {"value": rate, "unit": "cell-updates/s", "cores": threads,
+        t0 = time.perf_counter()
+        ref = oracle.solve_many(sample, threads=threads, fields=False)
+        cdt = time.perf_counter() - t0
+        errs = [rel(batch_out[k]["dft"], r["dft"]) for k, r in zip(sample_idx, ref)]
+        error = {"dft_rel_l2_max": float(max(errs)),
+                 "dft_rel_l2_median": float(np.median(errs)),
+                 "vs": "FP64 oracle", "precision": args.precision,
+                 "sample": f"{len(sample)} runs of the timed batch at their full "
+                           "step counts (batch order, each <= 4e9 cell-updates)"}
+        cpu = {"value": acc / cdt, "unit": "cell-updates/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"first {len(sample)} runs of the same seeded batch, "
-                         f"each stepped min(4 nz, {args.cpu_sample_steps}) steps "
-                         f"({sum(p.nz * p.steps for p in sample):.3g} "
-                         f"cell-updates, {cdt:.1f} s)"}
-        log(f"cpu oracle: {rate:.4g} cell-updates/s on {threads} threads; "
-            f"gpu error max {error['trace_rel_l2_max']:.2e}")
+               "sample": f"{len(sample)} runs of the same seeded batch at full length "
+                         f"({acc:.3g} cell-updates, {cdt:.1f} s), one run per thread"}
+        log(f"cpu oracle: {cpu['value']:.4g} cell-updates/s on {threads} threads; "
+            f"gpu DFT error max {error['dft_rel_l2_max']:.2e}")
 
     line = {
         "metric": METRIC,

@@ -1071,8 +1071,9 @@ gfdtd_status copy_results(const char *ws, const RunHost &r, const gfdtd_result *
         return hip_fail(e, "copy DFT");
     std::vector<double> trace;
     const bool want_trace = out->trace && (p.flags & GFDTD_FLAG_RECORD_TRACE);
-    // the trace is always read back for the blow-up check when present
-    if (np > 0 && r.steps > 0) {
+    // The blow-up check reads the DFT: a non-finite trace value makes its
+    // sums non-finite.  Without frequencies it reads the trace instead.
+    if (np > 0 && r.steps > 0 && (want_trace || nf == 0)) {
         trace.resize((size_t)np * r.steps);
         if ((e = hipMemcpyAsync(trace.data(), ws + r.L.trace, trace.size() * 8,
                                 hipMemcpyDeviceToHost, stream)))

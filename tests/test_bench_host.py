@@ -22,16 +22,22 @@ def test_saturated_rate_is_the_middle_slope():
 
 
 def test_traffic_counters_only_for_their_kernel_and_tiling(tmp_path, monkeypatch):
-    fields = dict(line.split(": ") for line in open(bench.COUNTERS).read().splitlines()
-                  if line and not line.startswith("#"))
-    C, T = int(fields["cells_per_lane"]), int(fields["block_steps"])
-    v = bench.measured_traffic_per_update(C, T)
-    assert v is not None and 0.0 < v < 16.0
-    assert bench.measured_traffic_per_update(C, T + 8) is None
+    import hashlib
+    import workloads as W
+    sha = hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()
+    prof = tmp_path / "counters.txt"
+    prof.write_text("# scaled counters\n"
+                    f"kernel_source_sha256: {sha}\ncells_per_lane: 16\nblock_steps: 48\n"
+                    "fetch_bytes_per_update: 0.4\nwrite_bytes_per_update: 0.2\n")
+    monkeypatch.setitem(bench.COUNTERS, W.F32, str(prof))
+    v = bench.measured_traffic_per_update(16, 48)
+    assert v is not None and abs(v - 0.6) < 1e-12
+    assert bench.measured_traffic_per_update(16, 56) is None
+    assert bench.measured_traffic_per_update(12, 48) is None
     other = tmp_path / "kernels.hip"
     other.write_text("// not the profiled source\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(other))
-    assert bench.measured_traffic_per_update(C, T) is None
+    assert bench.measured_traffic_per_update(16, 48) is None
 
 
 class _FakeServer:
@@ -101,6 +107,24 @@ def test_serving_driver_counts_latency_and_queueing(monkeypatch):
     # waits for admission: 0, 3, 6, 9 s (the queue, as sampled after each
     # progress call, holds 3, 2, 1 requests for 3 s each) -> mean 4.5 s
     assert abs(res["queue_wait_mean_s"] - 4.5) < 1e-9
+    # time averages of the sampled live and queued counts
+    assert 0.0 < res["live_mean"] <= 1.0 and 0.0 < res["queue_mean"] <= 3.0
+
+
+def test_alone_latency_driver(monkeypatch):
+    clock = {"t": 0.0}
+    monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])
+    fake = _FakeServer(work=2)
+    orig = fake.progress
+
+    def progress(max_blocks=1):
+        clock["t"] += 0.5
+        return orig(max_blocks)
+
+    fake.progress = progress
+    P = types.SimpleNamespace(Server=lambda **kw: fake)
+    prob = types.SimpleNamespace(nz=10, steps=5)
+    assert bench.alone_latencies(P, [prob, prob], 1 << 20, 8) == [1.0, 1.0]
 
 
 def test_more_than_one_gpu_is_refused():
