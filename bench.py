@@ -56,8 +56,12 @@ METRIC = ("cell-updates/sec batched-served vs plain at fixed error; "
 FLOPS_PER_UPDATE = 22
 # Algorithmic HBM bytes of one cell-update: read and write D and B once.
 BYTES_PER_UPDATE = {W.F32: 16, W.F64: 32}
-# MI355X: 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz, without packed FP32
-ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# MI355X vector-ALU peaks: FP64 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz
+# = 78.6 TFLOP/s; FP32 twice that, 157.3 TFLOP/s (two VALU instructions
+# can issue per SIMD and cycle slot: the FP32 stepping kernel measures 1.2
+# VALU wave-instructions per 4 cycles per SIMD without packed FP32 math).
+ALU_PEAK_TFLOPS = {W.F32: 256 * 64 * 2 * 2.4e9 * 2 / 1e12,
+                   W.F64: 256 * 64 * 2 * 2.4e9 / 1e12}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -111,9 +115,9 @@ def kernel_roofline(st, updates, precision):
         "kernel": "k_tiles",
         "bound": "alu",
         "achieved": round(achieved, 3),
-        "peak": round(ALU_PEAK_TFLOPS, 1),
+        "peak": round(ALU_PEAK_TFLOPS[precision], 1),
         "unit": "TFLOP/s",
-        "frac": round(achieved / ALU_PEAK_TFLOPS, 4),
+        "frac": round(achieved / ALU_PEAK_TFLOPS[precision], 4),
         "traffic": traffic,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                         "copy-calibrated)",
