@@ -9,6 +9,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "stepper.c")
 LIB = os.path.join(HERE, "liboracle.so")
+SRC2D = os.path.join(HERE, "stepper2d.c")
+LIB2D = os.path.join(HERE, "liboracle2d.so")
 
 
 def compile_stepper(src: str, out: str, verbose: bool = False) -> str:
@@ -24,6 +26,7 @@ def compile_stepper(src: str, out: str, verbose: bool = False) -> str:
 
 
 def build(verbose: bool = False) -> str:
+    compile_stepper(SRC2D, LIB2D, verbose)
     return compile_stepper(SRC, LIB, verbose)
 
 

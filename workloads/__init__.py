@@ -533,3 +533,143 @@ def tmm_crystals(seed: int, count: int, nomega: int = 256
         out.append(TmmStack(eps=eps, widths=widths, beta=beta))
     omega0 = 2.0 * math.pi / LAMBDA0
     return out, np.linspace(0.2 * omega0, 3.0 * omega0, nomega)
+
+
+# --------------------------------------------------------------------------
+# 2D runs: TE / TM in the (x, z) plane, motion along z, a stratified
+# moving modulation (interfaces normal to the velocity, as Section 3
+# assumes), x periodic
+# --------------------------------------------------------------------------
+
+TE = 0              # E_y, H_x, H_z
+TM = 1              # H_y, E_x, E_z
+
+
+@dataclasses.dataclass
+class Problem2D:
+    """One 2D solve.  Columns i = 0..nx-1 along x (periodic), z nodes as in
+    the 1D grid.  The modulation is stratified: eps_rest and mu_rest hold
+    one value per rest cell along z (nz entries each, the same cells as in
+    1D).  The source is a line along x at z node src_row: src_profile[i] times
+    the pulse, added to the D component of the 1D pair (D_y for TE, D_x for
+    TM).  Probes sit at (probe_x[q], probe_z[q]).
+
+    Field arrays (init_* and results) are (nx, nz), row i = column i of the
+    grid:  TE  D = D_y(i, k),  B = B_x(i, k+1/2),  C = B_z(i+1/2, k);
+           TM  D = D_x(i+1/2, k),  B = B_y(i+1/2, k+1/2),  C = D_z(i, k+1/2).
+    On a grid with ends the last entry of each row of B (and of C for TM)
+    is unused."""
+    pol: int
+    nx: int
+    nz: int
+    steps: int
+    eps_rest: np.ndarray
+    mu_rest: np.ndarray
+    courant: float = STEADY_COURANT
+    beta: float = 0.0
+    precision: int = F64
+    src_row: int = 200
+    src_profile: Optional[np.ndarray] = None
+    pulse: Pulse = dataclasses.field(default_factory=Pulse)
+    probe_x: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.zeros(0, dtype=np.int64))
+    probe_z: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.zeros(0, dtype=np.int64))
+    omegas: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.zeros(0, dtype=np.float64))
+    abc: int = ABC_MUR1
+    flags: int = 0
+    label: str = ""
+    init_d: Optional[np.ndarray] = None
+    init_b: Optional[np.ndarray] = None
+    init_c: Optional[np.ndarray] = None
+
+    def __post_init__(self):
+        self.eps_rest = np.ascontiguousarray(self.eps_rest, dtype=np.float64)
+        self.mu_rest = np.ascontiguousarray(self.mu_rest, dtype=np.float64)
+        if self.src_profile is None:
+            self.src_profile = np.ones(self.nx)
+        self.src_profile = np.ascontiguousarray(self.src_profile, dtype=np.float64)
+        self.probe_x = np.ascontiguousarray(self.probe_x, dtype=np.int64)
+        self.probe_z = np.ascontiguousarray(self.probe_z, dtype=np.int64)
+        self.omegas = np.ascontiguousarray(self.omegas, dtype=np.float64)
+        for k in ("init_d", "init_b", "init_c"):
+            a = getattr(self, k)
+            if a is not None:
+                setattr(self, k, np.ascontiguousarray(
+                    np.reshape(a, (self.nx, self.nz)), dtype=np.float64))
+
+    @property
+    def cell_updates(self) -> int:
+        return int(self.nx) * int(self.nz) * int(self.steps)
+
+    def replace(self, **kw) -> "Problem2D":
+        return dataclasses.replace(self, **kw)
+
+
+def oblique_profile(nx: int, m: int, pol: int, phase: float = 0.0) -> np.ndarray:
+    """Line-source profile cos(2 pi m x / nx + phase) sampled where the
+    sourced component lives: x = i (TE, D_y) or x = i + 1/2 (TM, D_x).  It
+    launches the +-k_x pair of waves at sin(theta) = k_x / (n omega) with
+    k_x = 2 pi m / nx."""
+    x = np.arange(nx, dtype=np.float64) + (0.5 if pol == TM else 0.0)
+    return np.cos(2.0 * math.pi * m * x / nx + phase)
+
+
+def slab_run_2d(seed: int = 0, pol: int = TE, precision: int = F32,
+                nx: int = 1024, nz: int = 16384, steps: int = 4096,
+                slab: int = 4096) -> Problem2D:
+    """Moving slab in 2D: nx x nz cells (x periodic), eps_s ~ U[2, 9],
+    beta ~ U[-0.6, 0.6] (stable draw), slab of `slab` cells centred on z;
+    a line source at z node 200 with an oblique profile of m ~ U{1..nx/64}
+    periods across x (up to 0.6 of the carrier's free-space k at
+    lambda0 = 40 cells), probes at z = 100 and nz - 100 on four columns."""
+    rng = np.random.default_rng(seed)
+    eps_s = float(rng.uniform(2.0, 9.0))
+    beta = draw_beta(rng, -0.6, 0.6, math.sqrt(eps_s))
+    phase = float(rng.uniform(0.0, 2.0 * math.pi))
+    m = int(rng.integers(1, max(2, nx // 64) + 1))
+    pulse = carrier_pulse(phase=phase)
+    start = nz // 2 - slab // 2
+    px = np.array([0, nx // 4, nx // 2, 3 * nx // 4] * 2, dtype=np.int64)
+    pz = np.array([100] * 4 + [nz - 100] * 4, dtype=np.int64)
+    return Problem2D(pol=pol, nx=nx, nz=nz, steps=steps,
+                     eps_rest=slab_profile(nz, start, slab, eps_s),
+                     mu_rest=uniform(nz), beta=beta, precision=precision,
+                     src_row=200, src_profile=oblique_profile(nx, m, pol),
+                     pulse=pulse, probe_x=px, probe_z=pz,
+                     omegas=default_omegas(pulse.omega, 32),
+                     label=f"slab2d_{'te' if pol == TE else 'tm'}")
+
+
+def small_case_2d(nx: int, nz: int, steps: int, beta: float, pol: int = TE,
+                  precision: int = F64, seed: int = 0, abc: int = ABC_MUR1,
+                  m: int = 1, structure: str = "slab",
+                  nfreq: int = 8) -> Problem2D:
+    """A short seeded 2D run for parity tests: random stratified eps
+    (slab or random cells) and mu ~ U[1, 1.5] per cell, an oblique line
+    source near the lower z end, probes spread over both axes."""
+    rng = np.random.default_rng(seed)
+    lam = 20.0
+    pulse = Pulse(amp=1.0, omega=2.0 * math.pi / lam, t0=40.0, tau=12.0,
+                  phase=float(rng.uniform(0, 2 * math.pi)), t_off=80.0)
+    if structure == "slab":
+        a = int(rng.integers(nz // 4, nz // 2))
+        eps = slab_profile(nz, a, max(1, nz // 4), float(rng.uniform(2.0, 4.0)))
+    elif structure == "random":
+        eps = rng.uniform(1.0, 3.0, size=nz)
+    else:
+        eps = uniform(nz)
+    mu = rng.uniform(1.0, 1.5, size=nz)
+    nmax = math.sqrt(float(np.max(eps)) * float(np.max(mu)))
+    if abs(beta) * nmax > LUMINAL_MARGIN:
+        beta = math.copysign(LUMINAL_MARGIN / nmax * 0.95, beta)
+    src = max(1, min(nz - 2, nz // 8))
+    pz = np.clip(np.array([0, src + 1, nz // 2, nz - 1, nz - 3]), 0, nz - 1)
+    px = np.array([0, nx - 1, nx // 2, 1 % nx, nx // 3])
+    return Problem2D(pol=pol, nx=nx, nz=nz, steps=steps, eps_rest=eps,
+                     mu_rest=mu, courant=0.5, beta=beta, precision=precision,
+                     src_row=src, src_profile=oblique_profile(nx, m, pol),
+                     pulse=pulse, probe_x=px, probe_z=pz,
+                     omegas=default_omegas(pulse.omega, nfreq), abc=abc,
+                     label=f"small2d_{structure}")
