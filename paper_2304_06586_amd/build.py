@@ -19,7 +19,8 @@ BUILD = os.path.join(PKG, "_build")
 ARCH = os.environ.get("GFDTD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp", "tmm.hip", "static_ws.hip"]
+SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp", "tmm.hip", "static_ws.hip",
+           "kernels2d.hip", "runtime2d.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]

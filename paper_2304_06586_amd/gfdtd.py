@@ -9,7 +9,7 @@ Problem descriptors are duck-typed: any object with the attributes of
 `workloads.Problem` (nz, steps, courant, beta, kind, precision, abc,
 flags, eps_rest, mu_rest, src_cell, pulse.{amp, omega, t0, tau, phase,
 t_off}, probes, omegas, and optionally init_d / init_b and window
-(t_on, t_off, eps_bg, mu_bg)).
+(t_on, t_off, eps_bg, mu_bg)); 2D ones those of `workloads.Problem2D`.
 """
 from __future__ import annotations
 
@@ -106,6 +106,51 @@ class gfdtd_server_config(C.Structure):
     ]
 
 
+GFDTD2D_TE = 0
+GFDTD2D_TM = 1
+
+
+class gfdtd2d_problem(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("pol", C.c_int32),
+        ("precision", C.c_int32), ("abc", C.c_int32), ("flags", C.c_uint32),
+        ("nprobe", C.c_int32), ("nfreq", C.c_int32), ("reserved0", C.c_int32),
+        ("nx", C.c_int64), ("nz", C.c_int64),
+        ("courant", C.c_double), ("beta", C.c_double),
+        ("eps_rest", _PD), ("mu_rest", _PD), ("src_row", C.c_int64),
+        ("src_profile", _PD),
+        ("src_amp", C.c_double), ("src_omega", C.c_double),
+        ("src_t0", C.c_double), ("src_tau", C.c_double),
+        ("src_phase", C.c_double), ("src_t_off", C.c_double),
+        ("probe_x", _PI64), ("probe_z", _PI64), ("omegas", _PD),
+        ("init_d", _PD), ("init_b", _PD), ("init_c", _PD),
+    ]
+
+
+class gfdtd2d_result(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("run_status", C.c_int32),
+        ("steps_done", C.c_int64), ("trace", _PD), ("dft_re", _PD),
+        ("dft_im", _PD), ("final_d", _PD), ("final_b", _PD), ("final_c", _PD),
+    ]
+
+
+class gfdtd2d_exec(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("cells_per_lane", C.c_int32),
+        ("columns_per_wave", C.c_int32), ("reserved0", C.c_int32),
+    ]
+
+
+class gfdtd2d_stats(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("cells_per_lane", C.c_int32),
+        ("columns_per_wave", C.c_int32), ("waves", C.c_int32),
+        ("launches", C.c_int64), ("cell_updates", C.c_double),
+        ("step_ms", C.c_double), ("pass_ms", C.c_double),
+    ]
+
+
 class GfdtdError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"gfdtd status {status}: {message}")
@@ -162,6 +207,20 @@ EXPORTS = {
     "gfdtd_tmm": (C.c_int, [C.POINTER(gfdtd_tmm_stack), C.c_int32, _PD, C.c_int32,
                             C.c_void_p, C.c_size_t, C.c_void_p, _PD, _PD]),
     "gfdtd_tmm_kernel_ms": (C.c_int, [C.POINTER(C.c_double)]),
+    # 2D path (include/gfdtd2d.h)
+    "gfdtd2d_check": (C.c_int, [C.POINTER(gfdtd2d_problem), C.c_int64,
+                                C.POINTER(C.c_double)]),
+    "gfdtd2d_workspace_bytes": (C.c_int, [C.POINTER(gfdtd2d_problem), C.c_int64,
+                                          C.POINTER(C.c_size_t)]),
+    "gfdtd2d_prepare": (C.c_int, [C.POINTER(gfdtd2d_problem), C.c_int64,
+                                  C.POINTER(gfdtd2d_exec), C.c_void_p, C.c_size_t,
+                                  C.c_void_p, C.POINTER(C.c_void_p)]),
+    "gfdtd2d_run_pass": (C.c_int, [C.c_void_p]),
+    "gfdtd2d_collect": (C.c_int, [C.c_void_p, C.POINTER(gfdtd2d_result)]),
+    "gfdtd2d_get_stats": (C.c_int, [C.c_void_p, C.POINTER(gfdtd2d_stats)]),
+    "gfdtd2d_destroy": (None, [C.c_void_p]),
+    "gfdtd2d_solve": (C.c_int, [C.POINTER(gfdtd2d_problem), C.c_int64, C.c_void_p,
+                                C.c_size_t, C.c_void_p, C.POINTER(gfdtd2d_result)]),
 }
 
 
@@ -586,6 +645,186 @@ class Server:
     def close(self):
         if self._h:
             self._lib.gfdtd_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ 2D path
+
+class _Marshalled2D:
+    """A gfdtd2d_problem struct plus the numpy arrays it points into."""
+
+    def __init__(self, p, steps: Optional[int] = None):
+        self.nx, self.nz = int(p.nx), int(p.nz)
+        self.eps = np.ascontiguousarray(p.eps_rest, dtype=np.float64)
+        self.mu = np.ascontiguousarray(p.mu_rest, dtype=np.float64)
+        prof = getattr(p, "src_profile", None)
+        self.prof = None if prof is None else np.ascontiguousarray(prof, dtype=np.float64)
+        self.px = np.ascontiguousarray(p.probe_x, dtype=np.int64)
+        self.pz = np.ascontiguousarray(p.probe_z, dtype=np.int64)
+        self.omegas = np.ascontiguousarray(p.omegas, dtype=np.float64)
+        self.steps = int(p.steps if steps is None else steps)
+        self.nprobe = len(self.px)
+        self.nfreq = len(self.omegas)
+        if len(self.pz) != self.nprobe:
+            raise ValueError("probe_x and probe_z differ in length")
+        s = gfdtd2d_problem()
+        s.struct_size = C.sizeof(gfdtd2d_problem)
+        s.pol = int(p.pol)
+        s.precision = int(p.precision)
+        s.abc = int(p.abc)
+        s.flags = int(getattr(p, "flags", 0))
+        s.nprobe = self.nprobe
+        s.nfreq = self.nfreq
+        s.nx, s.nz = self.nx, self.nz
+        s.courant = float(p.courant)
+        s.beta = float(p.beta)
+        s.eps_rest = self.eps.ctypes.data_as(_PD)
+        s.mu_rest = self.mu.ctypes.data_as(_PD)
+        s.src_row = int(p.src_row)
+        s.src_profile = None if self.prof is None else self.prof.ctypes.data_as(_PD)
+        s.src_amp = float(p.pulse.amp)
+        s.src_omega = float(p.pulse.omega)
+        s.src_t0 = float(p.pulse.t0)
+        s.src_tau = float(p.pulse.tau)
+        s.src_phase = float(p.pulse.phase)
+        s.src_t_off = float(p.pulse.t_off)
+        s.probe_x = self.px.ctypes.data_as(_PI64) if self.nprobe else None
+        s.probe_z = self.pz.ctypes.data_as(_PI64) if self.nprobe else None
+        s.omegas = self.omegas.ctypes.data_as(_PD) if self.nfreq else None
+        self.init = []
+        for name in ("init_d", "init_b", "init_c"):
+            a = getattr(p, name, None)
+            if a is not None:
+                a = np.ascontiguousarray(np.reshape(a, (self.nx * self.nz,)),
+                                         dtype=np.float64)
+                self.init.append(a)
+                setattr(s, name, a.ctypes.data_as(_PD))
+            else:
+                setattr(s, name, None)
+        self.struct = s
+
+
+class _ResultBuffers2D:
+    def __init__(self, m: _Marshalled2D, fields: bool = True, trace: bool = True):
+        self.trace = np.zeros((m.nprobe, m.steps if trace else 0))
+        self.dre = np.zeros((m.nprobe, m.nfreq))
+        self.dim = np.zeros((m.nprobe, m.nfreq))
+        shape = (m.nx, m.nz)
+        self.f = {k: (np.zeros(shape) if fields else None) for k in ("d", "b", "c")}
+        r = gfdtd2d_result()
+        r.struct_size = C.sizeof(gfdtd2d_result)
+        r.trace = self.trace.ctypes.data_as(_PD) if self.trace.size else None
+        r.dft_re = self.dre.ctypes.data_as(_PD) if self.dre.size else None
+        r.dft_im = self.dim.ctypes.data_as(_PD) if self.dim.size else None
+        for k in ("d", "b", "c"):
+            a = self.f[k]
+            setattr(r, "final_" + k, None if a is None else a.ctypes.data_as(_PD))
+        self.struct = r
+
+    def as_dict(self) -> Dict[str, np.ndarray]:
+        out = {"trace": self.trace, "dft": self.dre + 1j * self.dim,
+               "status": int(self.struct.run_status),
+               "steps_done": int(self.struct.steps_done)}
+        for k, a in self.f.items():
+            if a is not None:
+                out[k] = a
+        return out
+
+
+def gfdtd2d_check(problem, steps: Optional[int] = None) -> float:
+    """Validate a 2D problem and return the largest amplification factor
+    per step of the pre-flight (raises GfdtdError on E_INVALID, and on
+    E_UNSTABLE when the worst mode would grow more than tenfold over
+    `steps`, default problem.steps)."""
+    lib = load_library()
+    m = _Marshalled2D(problem, steps)
+    g = C.c_double(0.0)
+    _check(lib.gfdtd2d_check(C.byref(m.struct), m.steps, C.byref(g)))
+    return g.value
+
+
+def gfdtd2d_workspace_bytes(problem, steps: Optional[int] = None) -> int:
+    lib = load_library()
+    m = _Marshalled2D(problem, steps)
+    n = C.c_size_t(0)
+    _check(lib.gfdtd2d_workspace_bytes(C.byref(m.struct), m.steps, C.byref(n)))
+    return n.value
+
+
+def gfdtd2d_solve(problem, steps: Optional[int] = None, stream=None,
+                  fields: bool = True) -> Dict[str, np.ndarray]:
+    """One 2D solve (synchronous).  Returns trace (nprobe, steps), dft
+    (nprobe, nfreq) complex and the final d, b, c as (nx, nz) FP64 arrays."""
+    lib = load_library()
+    m = _Marshalled2D(problem, steps)
+    m.struct.flags |= GFDTD_FLAG_RECORD_TRACE
+    n = C.c_size_t(0)
+    _check(lib.gfdtd2d_workspace_bytes(C.byref(m.struct), m.steps, C.byref(n)))
+    ws = _device_buffer(n.value)
+    out = _ResultBuffers2D(m, fields)
+    _check(lib.gfdtd2d_solve(C.byref(m.struct), m.steps, C.c_void_p(ws.data_ptr()),
+                             n.value, _stream_handle(stream), C.byref(out.struct)))
+    return out.as_dict()
+
+
+class Run2D:
+    """gfdtd2d_prepare / run_pass / collect / get_stats / destroy."""
+
+    def __init__(self, problem, steps=None, cells_per_lane=0, columns_per_wave=0,
+                 stream=None, record_trace=True, fields=True):
+        import torch
+        self._lib = load_library()
+        self._m = _Marshalled2D(problem, steps)
+        if record_trace:
+            self._m.struct.flags |= GFDTD_FLAG_RECORD_TRACE
+        self._fields = fields
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        n = C.c_size_t(0)
+        _check(self._lib.gfdtd2d_workspace_bytes(C.byref(self._m.struct), self._m.steps,
+                                                 C.byref(n)))
+        self.workspace_bytes = n.value
+        self._ws = _device_buffer(n.value)
+        e = gfdtd2d_exec()
+        e.struct_size = C.sizeof(gfdtd2d_exec)
+        e.cells_per_lane = int(cells_per_lane)
+        e.columns_per_wave = int(columns_per_wave)
+        self._exec = e
+        h = C.c_void_p(None)
+        _check(self._lib.gfdtd2d_prepare(
+            C.byref(self._m.struct), self._m.steps, C.byref(e),
+            C.c_void_p(self._ws.data_ptr()), n.value, _stream_handle(self.stream),
+            C.byref(h)))
+        self._h = h
+
+    def run(self):
+        _check(self._lib.gfdtd2d_run_pass(self._h))
+
+    def collect(self) -> Dict[str, np.ndarray]:
+        out = _ResultBuffers2D(self._m, self._fields)
+        _check(self._lib.gfdtd2d_collect(self._h, C.byref(out.struct)))
+        return out.as_dict()
+
+    def stats(self) -> Dict[str, float]:
+        s = gfdtd2d_stats()
+        s.struct_size = C.sizeof(gfdtd2d_stats)
+        _check(self._lib.gfdtd2d_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in gfdtd2d_stats._fields_ if k != "struct_size"}
+
+    def close(self):
+        if self._h:
+            self._lib.gfdtd2d_destroy(self._h)
             self._h = None
 
     def __enter__(self):

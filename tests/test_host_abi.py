@@ -14,7 +14,7 @@ import workloads as W
 from oracle import stability as st
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gfdtd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gfdtd.h", "gfdtd2d.h")]
 
 
 @pytest.fixture(scope="module")
@@ -29,9 +29,12 @@ def P():
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gfdtd_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(gfdtd2?d?_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_functions_are_exported(P):
@@ -54,9 +57,10 @@ def test_struct_sizes_match_header(P, tmp_path):
     import subprocess
     g = P.gfdtd
     structs = ["gfdtd_problem", "gfdtd_result", "gfdtd_exec", "gfdtd_stats",
-               "gfdtd_server_config", "gfdtd_tmm_stack"]
+               "gfdtd_server_config", "gfdtd_tmm_stack", "gfdtd2d_problem",
+               "gfdtd2d_result", "gfdtd2d_exec", "gfdtd2d_stats"]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gfdtd.h"',
-             "int main(void) {"]
+             '#include "gfdtd2d.h"', "int main(void) {"]
     for name in structs:
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
         for f, _ in getattr(g, name)._fields_:

@@ -102,7 +102,7 @@ def _textbook_yee(p):
     """Plain 2D Yee in (D, B) form, x periodic, PEC z ends, soft source on
     D: arrays (nx, nz), shifts by np.roll / slicing.  Each node reads the
     rest cell containing it: eps cells [i-1/2, i+1/2), mu cells [i, i+1)."""
-    nx, nz = p.nx, p.nz
+    nx, nz, S = p.nx, p.nz, p.courant
     eps, mu = p.eps_rest, p.mu_rest
     eps_e = eps                           # E-lattice node z = k
     mu_h = mu[:nz - 1]                    # H-lattice node z = j + 1/2

@@ -616,27 +616,34 @@ def oblique_profile(nx: int, m: int, pol: int, phase: float = 0.0) -> np.ndarray
     return np.cos(2.0 * math.pi * m * x / nx + phase)
 
 
+COURANT_2D = 0.25
+
+
 def slab_run_2d(seed: int = 0, pol: int = TE, precision: int = F32,
-                nx: int = 1024, nz: int = 16384, steps: int = 4096,
-                slab: int = 4096) -> Problem2D:
-    """Moving slab in 2D: nx x nz cells (x periodic), eps_s ~ U[2, 9],
-    beta ~ U[-0.6, 0.6] (stable draw), slab of `slab` cells centred on z;
-    a line source at z node 200 with an oblique profile of m ~ U{1..nx/64}
-    periods across x (up to 0.6 of the carrier's free-space k at
-    lambda0 = 40 cells), probes at z = 100 and nz - 100 on four columns."""
+                nx: int = 4096, nz: int = 4096, steps: int = 4096,
+                slab: int = 1024) -> Problem2D:
+    """Moving slab in 2D: nx x nz cells (x periodic), S = 0.25, eps_s ~
+    U[2, 9], beta ~ U[-0.6, 0.6] (stable draw), a slab of `slab` cells
+    starting at nz/4 - 256 along z; a 10-cycle carrier pulse (lambda0 = 40
+    cells) from a line source at z node 200 with an oblique profile of
+    m ~ U{1..nx/64} periods across x (up to 0.63 of the carrier's free-space
+    wavenumber), probes at z = 100 and nz - 100 on four columns each.  The
+    duration (steps S = 1024 at the defaults) carries the pulse across the
+    slab."""
     rng = np.random.default_rng(seed)
     eps_s = float(rng.uniform(2.0, 9.0))
     beta = draw_beta(rng, -0.6, 0.6, math.sqrt(eps_s))
     phase = float(rng.uniform(0.0, 2.0 * math.pi))
     m = int(rng.integers(1, max(2, nx // 64) + 1))
-    pulse = carrier_pulse(phase=phase)
-    start = nz // 2 - slab // 2
+    pulse = carrier_pulse(cycles=10.0, phase=phase)
+    start = max(0, nz // 4 - 256)
     px = np.array([0, nx // 4, nx // 2, 3 * nx // 4] * 2, dtype=np.int64)
     pz = np.array([100] * 4 + [nz - 100] * 4, dtype=np.int64)
     return Problem2D(pol=pol, nx=nx, nz=nz, steps=steps,
                      eps_rest=slab_profile(nz, start, slab, eps_s),
-                     mu_rest=uniform(nz), beta=beta, precision=precision,
-                     src_row=200, src_profile=oblique_profile(nx, m, pol),
+                     mu_rest=uniform(nz), courant=COURANT_2D, beta=beta,
+                     precision=precision, src_row=200,
+                     src_profile=oblique_profile(nx, m, pol),
                      pulse=pulse, probe_x=px, probe_z=pz,
                      omegas=default_omegas(pulse.omega, 32),
                      label=f"slab2d_{'te' if pol == TE else 'tm'}")
@@ -646,8 +653,8 @@ def small_case_2d(nx: int, nz: int, steps: int, beta: float, pol: int = TE,
                   precision: int = F64, seed: int = 0, abc: int = ABC_MUR1,
                   m: int = 1, structure: str = "slab",
                   nfreq: int = 8) -> Problem2D:
-    """A short seeded 2D run for parity tests: random stratified eps
-    (slab or random cells) and mu ~ U[1, 1.5] per cell, an oblique line
+    """A short seeded 2D run for parity tests: S = 0.25, random stratified
+    eps (slab or random cells) and mu ~ U[1, 1.5] per cell, an oblique line
     source near the lower z end, probes spread over both axes."""
     rng = np.random.default_rng(seed)
     lam = 20.0
@@ -668,7 +675,7 @@ def small_case_2d(nx: int, nz: int, steps: int, beta: float, pol: int = TE,
     pz = np.clip(np.array([0, src + 1, nz // 2, nz - 1, nz - 3]), 0, nz - 1)
     px = np.array([0, nx - 1, nx // 2, 1 % nx, nx // 3])
     return Problem2D(pol=pol, nx=nx, nz=nz, steps=steps, eps_rest=eps,
-                     mu_rest=mu, courant=0.5, beta=beta, precision=precision,
+                     mu_rest=mu, courant=COURANT_2D, beta=beta, precision=precision,
                      src_row=src, src_profile=oblique_profile(nx, m, pol),
                      pulse=pulse, probe_x=px, probe_z=pz,
                      omegas=default_omegas(pulse.omega, nfreq), abc=abc,
