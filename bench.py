@@ -28,6 +28,12 @@ Printed beside it, in the same JSON line:
                   the host;
   tmm_sweep    -- the batched transfer-matrix evaluator: call and kernel
                   time;
+  twod         -- the 2D TE / TM path on a moving slab (4096 x 4096 cells,
+                  x periodic, 4096 steps at S = 0.25), FP32 and FP64: rate,
+                  the step kernel (k_step2d) against the HBM peak at its
+                  algorithmic 6 words per cell-update, FP32 against FP64 at
+                  full size, and the 2D oracle's error and host rate on a
+                  64-column copy of 1024 steps;
   error        -- the FP32 batch's probe spectra against the oracle on a
                   sample of its runs at their full step counts;
   cpu_baseline -- the oracle on the host cores on that sample.
@@ -74,6 +80,13 @@ COUNTERS = {
     W.F64: os.path.join(ROOT, "profiles", "k_tiles_f64_crystals4096_hbm_counters.txt"),
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels.hip")
+KERNEL2D_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels2d.hip")
+COUNTERS_2D = {
+    (W.TE, W.F32): os.path.join(ROOT, "profiles", "k_step2d_f32_te_slab4096_hbm_counters.txt"),
+    (W.TE, W.F64): os.path.join(ROOT, "profiles", "k_step2d_f64_te_slab4096_hbm_counters.txt"),
+}
+# Algorithmic HBM bytes of one 2D cell-update: read and write D, B and C once.
+BYTES_PER_UPDATE_2D = {W.F32: 24, W.F64: 48}
 
 
 def measured_traffic_per_update(C, T, precision=W.F32):
@@ -96,6 +109,123 @@ def measured_traffic_per_update(C, T, precision=W.F32):
         return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic_2d(pol, precision, C, xch):
+    """HBM bytes per cell-update of k_step2d from committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE counters (copy-calibrated), or None when there
+    are none for this polarization and precision, the kernel source has
+    changed since, or they were taken at another tiling."""
+    import hashlib
+    path = COUNTERS_2D.get((pol, precision))
+    if path is None:
+        return None
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(KERNEL2D_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        if int(kv["cells_per_lane"]) != C or int(kv["columns_per_wave"]) != xch:
+            return None
+        return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def kernel_roofline_2d(st, pol, precision):
+    """k_step2d of the last pass against the HBM peak: algorithmic bytes per
+    launch (6 words per cell-update) over the average launch time from the
+    library's HIP events around the pass's stepping launches."""
+    launches = max(1, int(st["launches"]))
+    avg_launch_ms = st["step_ms"] / launches
+    upd_per_launch = st["cell_updates"] / launches
+    alg = upd_per_launch * BYTES_PER_UPDATE_2D[precision]
+    achieved = alg / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
+    per_update = measured_traffic_2d(pol, precision, int(st["cells_per_lane"]),
+                                     int(st["columns_per_wave"]))
+    traffic = per_update * upd_per_launch if per_update is not None else None
+    return {
+        "kernel": "k_step2d",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                        "copy-calibrated)",
+        "algorithmic_bytes_per_launch": alg,
+        "bytes_per_update": BYTES_PER_UPDATE_2D[precision],
+        "launches_per_pass": launches,
+        "avg_launch_ms": round(avg_launch_ms, 4),
+        "cells_per_lane": int(st["cells_per_lane"]),
+        "columns_per_wave": int(st["columns_per_wave"]),
+        "waves_per_launch": int(st["waves"]),
+    }
+
+
+def twod_leg(P, args):
+    """The 2D path on the moving-slab workload, both polarizations and
+    precisions: one untimed pass, then a timed pass (inputs resident)."""
+    import torch
+    out = {}
+    full = {}
+    cases = set(args.twod_cases.split(","))
+    for pol, pname in ((W.TE, "te"), (W.TM, "tm")):
+        for prec, dname in ((W.F32, "f32"), (W.F64, "f64")):
+            if f"{pname}_{dname}" not in cases:
+                continue
+            p = W.slab_run_2d(args.seed, pol=pol, precision=prec)
+            if args.twod_steps:
+                p = p.replace(steps=args.twod_steps)
+            with P.Run2D(p, fields=False) as r:
+                r.run()
+                r.collect()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r.run()
+                res = r.collect()
+                dt = time.perf_counter() - t0
+                st = r.stats()
+            full[(pname, dname)] = res
+            out[f"{pname}_{dname}"] = {
+                "value": p.cell_updates / dt, "unit": "cell-updates/s",
+                "ms": dt * 1e3, "nx": p.nx, "nz": p.nz, "steps": p.steps,
+                "beta": p.beta, "status": res["status"],
+                "roofline": kernel_roofline_2d(st, pol, prec)}
+            log(f"2d {pname}_{dname}: {p.cell_updates / dt:.4g} cell-updates/s, "
+                f"{dt * 1e3:.1f} ms, k_step2d {out[f'{pname}_{dname}']['roofline']['achieved']}"
+                f" GB/s (C={st['cells_per_lane']}, {st['columns_per_wave']} columns/wave)")
+    for pname in ("te", "tm"):
+        if (pname, "f64") not in full or (pname, "f32") not in full:
+            continue
+        a, b = full[(pname, "f64")], full[(pname, "f32")]
+        out[f"{pname}_f32"]["error_vs_gpu_f64"] = {
+            "trace_rel_l2": rel(b["trace"], a["trace"]),
+            "dft_rel_l2": rel(b["dft"], a["dft"])}
+    if not args.no_cpu and not args.twod_steps:
+        from oracle import stepper2d
+        for pol, pname in ((W.TE, "te"), (W.TM, "tm")):
+            if f"{pname}_f32" not in out or f"{pname}_f64" not in out:
+                continue
+            q = W.slab_run_2d(args.seed, pol=pol, precision=W.F64, nx=64, steps=1024)
+            t0 = time.perf_counter()
+            ref = stepper2d.solve(q, fields=False)
+            odt = time.perf_counter() - t0
+            for prec, dname in ((W.F32, "f32"), (W.F64, "f64")):
+                g = P.gfdtd2d_solve(q.replace(precision=prec), fields=False)
+                out[f"{pname}_{dname}"]["error_vs_oracle_downscaled"] = {
+                    "trace_rel_l2": rel(g["trace"], ref["trace"]),
+                    "dft_rel_l2": rel(g["dft"], ref["dft"])}
+            out[f"{pname}_f64"]["oracle"] = {
+                "value": q.cell_updates / odt, "unit": "cell-updates/s", "cores": 1,
+                "seconds": round(odt, 2),
+                "sample": "the same workload on 64 columns for 1024 steps"}
+    return out
 
 
 def kernel_roofline(st, updates, precision):
@@ -368,6 +498,11 @@ def main():
                     help="keep the default tiling instead of autotuning it")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-tmm", action="store_true")
+    ap.add_argument("--no-2d", action="store_true")
+    ap.add_argument("--twod-cases", default="te_f32,te_f64,tm_f32,tm_f64",
+                    help="2D cases to run (polarization_precision, comma-separated)")
+    ap.add_argument("--twod-steps", type=int, default=0, metavar="N",
+                    help="run the 2D cases for N steps instead of 4096 (profiling)")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75,0.9,1.1",
                     help="offered loads as fractions of the saturated request "
                          "rate, comma separated (the first also gets alone times)")
@@ -549,6 +684,11 @@ def main():
         log(f"transfer-matrix sweep: call {dt_call * 1e3:.2f} ms, kernel "
             f"{dt_kernel * 1e3:.3f} ms")
 
+    # ------------------------------------------------------------- 2D path
+    twod = None
+    if not args.no_2d:
+        twod = twod_leg(P, args)
+
     # ------------------- error and CPU baseline on a sample of the batch
     error = None
     cpu = None
@@ -612,6 +752,7 @@ def main():
         "batched_over_plain_slab": (value / plain[f"slab_{args.precision}"]["value"]
                                     if plain else None),
         "tmm_sweep": tmm,
+        "twod": twod,
         "error": error,
         "cpu_baseline": cpu,
     }

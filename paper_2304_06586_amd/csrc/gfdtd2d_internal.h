@@ -43,7 +43,8 @@ int64_t strip_rows(int C);
 Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch);
 
 hipError_t launch_prep2d(const Run2D *dev, const Run2D &host, hipStream_t s);
-hipError_t launch_step2d(const Run2D *dev, const Run2D &host, const Launch2D &L,
-                         int64_t n, int par, hipStream_t s);
+// One stepping launch; the descriptor travels by value as a kernel argument.
+hipError_t launch_step2d(const Run2D &host, const Launch2D &L, int64_t n, int par,
+                         hipStream_t s);
 
 }  // namespace gfdtd

@@ -112,14 +112,14 @@ template <typename R> struct Vec16;
 template <> struct Vec16<float> { using T = float4; };
 template <> struct Vec16<double> { using T = double2; };
 
-__device__ __forceinline__ int64_t clamp64(int64_t i, int64_t lo, int64_t hi)
+__device__ __forceinline__ int clampi(int i, int lo, int hi)
 {
     return i < lo ? lo : (i > hi ? hi : i);
 }
 
-__device__ __forceinline__ int64_t wrap64(int64_t i, int64_t n)
+__device__ __forceinline__ int wrapi(int i, int n)
 {
-    const int64_t r = i % n;
+    const int r = i % n;
     return r < 0 ? r + n : r;
 }
 
@@ -127,8 +127,8 @@ __device__ __forceinline__ int64_t wrap64(int64_t i, int64_t n)
 // per 16 bytes when they all lie on the lattice, else per row with the
 // edge value off the grid (wrapped on a z-ring).
 template <typename R, int C>
-__device__ __forceinline__ void load_rows(const R *__restrict__ col, int64_t r0,
-                                          int64_t n, int64_t nz, bool ring, R (&a)[C])
+__device__ __forceinline__ void load_rows(const R *__restrict__ col, int r0, int n, int nz,
+                                          bool ring, R (&a)[C])
 {
     if (r0 >= 0 && r0 + C <= n) {
         using V = typename Vec16<R>::T;
@@ -142,16 +142,16 @@ __device__ __forceinline__ void load_rows(const R *__restrict__ col, int64_t r0,
     } else {
 #pragma unroll
         for (int q = 0; q < C; ++q) {
-            const int64_t r = r0 + q;
-            a[q] = col[ring ? wrap64(r, nz) : clamp64(r, 0, n - 1)];
+            const int r = r0 + q;
+            a[q] = col[ring ? wrapi(r, nz) : clampi(r, 0, n - 1)];
         }
     }
 }
 
 // Store the rows of r0..r0+C-1 that lie in [lo, hi).
 template <typename R, int C>
-__device__ __forceinline__ void store_rows(R *__restrict__ col, int64_t r0, int64_t lo,
-                                           int64_t hi, const R (&a)[C])
+__device__ __forceinline__ void store_rows(R *__restrict__ col, int r0, int lo, int hi,
+                                           const R (&a)[C])
 {
     if (r0 >= lo && r0 + C <= hi) {
         using V = typename Vec16<R>::T;
@@ -166,7 +166,7 @@ __device__ __forceinline__ void store_rows(R *__restrict__ col, int64_t r0, int6
     } else {
 #pragma unroll
         for (int q = 0; q < C; ++q) {
-            const int64_t r = r0 + q;
+            const int r = r0 + q;
             if (r >= lo && r < hi)
                 col[r] = a[q];
         }
@@ -174,52 +174,59 @@ __device__ __forceinline__ void store_rows(R *__restrict__ col, int64_t r0, int6
 }
 
 // Rest cell under lattice position x when the profile has moved m cells.
-__device__ __forceinline__ int64_t rest_cell(int64_t x, int64_t m, int64_t hi,
-                                             int64_t nz, bool ring)
+__device__ __forceinline__ int rest_cell(int x, int m, int hi, int nz, bool ring)
 {
-    return ring ? wrap64(x - m, nz) : clamp64(x - m, 0, hi);
+    return ring ? wrapi(x - m, nz) : clampi(x - m, 0, hi);
 }
 
-__device__ __forceinline__ int64_t shift_at(double bS, double tau)
+// Whole-cell shift m = rint(beta S tau) as the index arithmetic needs it:
+// on a z-ring reduced modulo nz (indices wrap); otherwise clamped to
+// +-4 nz, which changes no index of a grid node (those clamp to the grid).
+__device__ __forceinline__ int shift_at(double bS, double tau, int nz, bool ring)
 {
-    return (int64_t)rint(bS * tau);
+    const int64_t m = (int64_t)rint(bS * tau);
+    if (ring) {
+        const int64_t r = m % nz;
+        return (int)(r < 0 ? r + nz : r);
+    }
+    const int64_t lim = 4 * (int64_t)nz;
+    return (int)(m > lim ? lim : (m < -lim ? -lim : m));
 }
 
 template <typename R, int C, bool TE, bool COLA>
-__global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, int64_t n,
-                                                int par, int xch, int64_t nstrips,
-                                                int64_t waves, int64_t blocks)
+__global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int par, int xch,
+                                                int nstrips, int waves, int blocks)
 {
-    const Run2D &rd = *rdp;
     const int lane = threadIdx.x & 63;
     // each XCD (blocks b = x mod 8) takes a contiguous range of wave ids
-    const int64_t b = blockIdx.x;
-    const int64_t lb = (b & 7) * (blocks >> 3) + (b >> 3);
-    const int64_t w = lb * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * (blocks >> 3) + (b >> 3);
+    const int w = lb * 4 + (int)(threadIdx.x >> 6);
     if (w >= waves)
         return;
     constexpr int STRIDE = 64 * C - 2 * HALO2D;
-    const int64_t s = w % nstrips;
-    const int64_t chunk = w / nstrips;
-    const int64_t nx = rd.nx, nz = rd.nz, ld = rd.ld, nh = rd.nh, nc = rd.nc;
+    const int s = w % nstrips;
+    const int chunk = w / nstrips;
+    const int nx = (int)rd.nx, nz = (int)rd.nz, nh = (int)rd.nh, nc = (int)rd.nc;
+    const int64_t ld = rd.ld;
     const bool ring = rd.abc == GFDTD_ABC_PERIODIC;
-    const int64_t vlo = s * STRIDE;
-    const int64_t vhi = vlo + STRIDE < nz ? vlo + STRIDE : nz;
-    const int64_t r0 = vlo - HALO2D + (int64_t)lane * C;
-    const int64_t i0 = chunk * xch;
-    const int64_t i1 = i0 + xch < nx ? i0 + xch : nx;
+    const int vlo = s * STRIDE;
+    const int vhi = vlo + STRIDE < nz ? vlo + STRIDE : nz;
+    const int r0 = vlo - HALO2D + lane * C;
+    const int i0 = chunk * xch;
+    const int i1 = i0 + xch < nx ? i0 + xch : nx;
 
     const double Sd = rd.S, betad = rd.beta, bSd = betad * Sd;
     const R S = (R)Sd, beta = (R)betad, bS = (R)bSd, half = (R)0.5;
-    const int64_t mEp = shift_at(bSd, (double)n - 0.5);   // E* of step n-1
-    const int64_t mH = shift_at(bSd, (double)n);
-    const int64_t mE = shift_at(bSd, (double)n + 0.5);
+    const int mEp = shift_at(bSd, (double)n - 0.5, nz, ring);   // E* of step n-1
+    const int mH = shift_at(bSd, (double)n, nz, ring);
+    const int mE = shift_at(bSd, (double)n + 0.5, nz, ring);
 
     // per-row material coefficients (z only)
     R ce[C], chB[C], cc[C];
 #pragma unroll
     for (int q = 0; q < C; ++q) {
-        const int64_t r = r0 + q;
+        const int r = r0 + q;
         ce[q] = (R)(1.0 / rd.eps[rest_cell(r, mEp, nz - 1, nz, ring)]);
         chB[q] = (R)(1.0 / rd.mu[rest_cell(r, mH, ring ? nz - 1 : nz - 2, nz, ring)]);
         if (TE)   // B_z at (i+1/2, k): mu cell k
@@ -228,24 +235,29 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
             cc[q] = (R)(1.0 / rd.eps[rest_cell(r + 1, mEp, nz - 1, nz, ring)]);
     }
 
-    const R *Din = static_cast<const R *>(rd.f[par]);
-    const R *Bin = static_cast<const R *>(rd.f[2 + par]);
-    const R *Cin = static_cast<const R *>(rd.f[4 + par]);
-    R *Dout = static_cast<R *>(rd.f[1 - par]);
-    R *Bout = static_cast<R *>(rd.f[3 - par]);
-    R *Cout = static_cast<R *>(rd.f[5 - par]);
-    auto colp = [&](const R *base, int64_t i) { return base + wrap64(i, nx) * ld; };
+    const R *Din = static_cast<const R *>(par ? rd.f[1] : rd.f[0]);
+    const R *Bin = static_cast<const R *>(par ? rd.f[3] : rd.f[2]);
+    const R *Cin = static_cast<const R *>(par ? rd.f[5] : rd.f[4]);
+    R *Dout = static_cast<R *>(par ? rd.f[0] : rd.f[1]);
+    R *Bout = static_cast<R *>(par ? rd.f[2] : rd.f[3]);
+    R *Cout = static_cast<R *>(par ? rd.f[4] : rd.f[5]);
+    // column i (i0 - 1 <= i <= i1 + 1) wrapped onto 0..nx-1
+    auto colp = [&](const R *base, int i) {
+        const int iw = nx == 1 ? 0 : (i < 0 ? i + nx : (i >= nx ? i - nx : i));
+        return base + (int64_t)iw * ld;
+    };
 
     // step-wide scalars: source sample, end coefficients, probes of this wave
-    const bool has_src = n <= rd.nsrc && rd.src_row >= vlo && rd.src_row < vhi;
+    const int src_row = (int)rd.src_row;
+    const bool has_src = n <= rd.nsrc && src_row >= vlo && src_row < vhi;
     const double g = has_src ? rd.src[n - 1] : 0.0;
     const bool left_end = !ring && vlo == 0;
     const bool right_end = !ring && vhi == nz;
     R cL = 0, cR = 0;
     if (rd.abc == GFDTD_ABC_MUR1 && (left_end || right_end)) {
-        const double nL = sqrt(rd.eps[clamp64(-mE, 0, nz - 1)] * rd.mu[clamp64(-mE, 0, nz - 2)]);
-        const double nR = sqrt(rd.eps[clamp64(nz - 1 - mE, 0, nz - 1)] *
-                               rd.mu[clamp64(nz - 2 - mE, 0, nz - 2)]);
+        const double nL = sqrt(rd.eps[clampi(-mE, 0, nz - 1)] * rd.mu[clampi(-mE, 0, nz - 2)]);
+        const double nR = sqrt(rd.eps[clampi(nz - 1 - mE, 0, nz - 1)] *
+                               rd.mu[clampi(nz - 2 - mE, 0, nz - 2)]);
         const double uL = 1.0 / nL, uR = 1.0 / nR;
         cL = (R)((Sd * uL - 1.0) / (Sd * uL + 1.0));
         cR = (R)((Sd * uR - 1.0) / (Sd * uR + 1.0));
@@ -291,12 +303,12 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
         }
     };
     // source, z ends and probes on the new D of column i, then store
-    auto finish_d = [&](int64_t i, const R (&Dold)[C], R (&Dn)[C]) {
+    auto finish_d = [&](int i, const R (&Dold)[C], R (&Dn)[C]) {
         if (has_src) {
             const double add = rd.prof[i] * g;
 #pragma unroll
             for (int q = 0; q < C; ++q)
-                if (r0 + q == rd.src_row)
+                if (r0 + q == src_row)
                     Dn[q] = (R)((double)Dn[q] + add);
         }
         if (rd.abc == GFDTD_ABC_MUR1) {
@@ -329,9 +341,9 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
                 const int q = __builtin_ctzll(m);
                 if (rd.px[q] != i)
                     continue;
-                const int64_t z = rd.pz[q];
-                const int64_t off = z - (vlo - HALO2D);
-                const int lp = (int)(off / C), qq = (int)(off % C);
+                const int z = (int)rd.pz[q];
+                const int off = z - (vlo - HALO2D);
+                const int lp = off / C, qq = off % C;
                 R v = Dn[0];
 #pragma unroll
                 for (int t = 1; t < C; ++t)
@@ -370,7 +382,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
         load_rows<R, C>(colp(Din, i0 + 1), r0, nz, nz, ring, Dl);
         load_rows<R, C>(colp(Bin, i0 + 1), r0, nh, nz, ring, Bl);
         load_rows<R, C>(colp(Cin, i0), r0, nc, nz, ring, Cl);
-        for (int64_t i = i0; i < i1; ++i) {
+        for (int i = i0; i < i1; ++i) {
             R Dx[C], Bx[C];
 #pragma unroll
             for (int q = 0; q < C; ++q) {
@@ -409,7 +421,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
             for (int q = 0; q < C; ++q)
                 Dn[q] = Dc[q] + S * (Hs[q] - t2[q]) - S * (Hc[q] - Hcp[q]) - bS * dd[q];
             finish_d(i, Dc, Dn);
-            const int64_t o = i * ld;
+            const int64_t o = (int64_t)i * ld;
             store_rows<R, C>(Dout + o, r0, vlo, vhi, Dn);
             store_rows<R, C>(Bout + o, r0, vlo, vhi < nh ? vhi : nh, Bn);
             store_rows<R, C>(Cout + o, r0, vlo, vhi < nc ? vhi : nc, Cn);
@@ -432,7 +444,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
         load_rows<R, C>(colp(Din, i0 - 1), r0, nz, nz, ring, Dl);
         load_rows<R, C>(colp(Bin, i0 - 1), r0, nh, nz, ring, Bl);
         load_rows<R, C>(colp(Cin, i0), r0, nc, nz, ring, Cl);
-        for (int64_t i = i0 - 1; i < i1; ++i) {
+        for (int i = i0 - 1; i < i1; ++i) {
             R Dc[C], Bc[C], Cx[C];
 #pragma unroll
             for (int q = 0; q < C; ++q) {
@@ -474,7 +486,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D *__restrict__ rdp, i
                 for (int q = 0; q < C; ++q)
                     Cn[q] = Cr[q] + S * (Hs[q] - Hsp[q]) - bS * dd[q];
                 finish_d(i, Dc, Dn);
-                const int64_t o = i * ld;
+                const int64_t o = (int64_t)i * ld;
                 store_rows<R, C>(Dout + o, r0, vlo, vhi, Dn);
                 store_rows<R, C>(Bout + o, r0, vlo, vhi < nh ? vhi : nh, Bn);
                 store_rows<R, C>(Cout + o, r0, vlo, vhi < nc ? vhi : nc, Cn);
@@ -520,23 +532,23 @@ __global__ __launch_bounds__(256) void k_prep2d(const Run2D *__restrict__ rdp)
 }
 
 template <typename R, int C>
-hipError_t step_as(const Run2D *dev, const Run2D &h, const Launch2D &L, int64_t n, int par,
-                   hipStream_t s)
+hipError_t step_as(const Run2D &h, const Launch2D &L, int64_t n, int par, hipStream_t s)
 {
     const dim3 grid((unsigned)L.blocks), block(256);
     const bool te = h.pol == GFDTD2D_TE, cola = h.beta >= 0.0;
+    const int xch = L.xch, ns = (int)L.nstrips, waves = (int)L.waves, blocks = (int)L.blocks;
     if (te && cola)
-        hipLaunchKernelGGL((k_step2d<R, C, true, true>), grid, block, 0, s, dev, n, par,
-                           L.xch, L.nstrips, L.waves, L.blocks);
+        hipLaunchKernelGGL((k_step2d<R, C, true, true>), grid, block, 0, s, h, n, par, xch,
+                           ns, waves, blocks);
     else if (te)
-        hipLaunchKernelGGL((k_step2d<R, C, true, false>), grid, block, 0, s, dev, n, par,
-                           L.xch, L.nstrips, L.waves, L.blocks);
+        hipLaunchKernelGGL((k_step2d<R, C, true, false>), grid, block, 0, s, h, n, par, xch,
+                           ns, waves, blocks);
     else if (cola)
-        hipLaunchKernelGGL((k_step2d<R, C, false, true>), grid, block, 0, s, dev, n, par,
-                           L.xch, L.nstrips, L.waves, L.blocks);
+        hipLaunchKernelGGL((k_step2d<R, C, false, true>), grid, block, 0, s, h, n, par, xch,
+                           ns, waves, blocks);
     else
-        hipLaunchKernelGGL((k_step2d<R, C, false, false>), grid, block, 0, s, dev, n, par,
-                           L.xch, L.nstrips, L.waves, L.blocks);
+        hipLaunchKernelGGL((k_step2d<R, C, false, false>), grid, block, 0, s, h, n, par, xch,
+                           ns, waves, blocks);
     return hipGetLastError();
 }
 
@@ -552,10 +564,13 @@ Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch)
     L.C = C;
     L.nstrips = (nz + strip_rows(C) - 1) / strip_rows(C);
     if (xch <= 0) {
-        // about 8 waves per SIMD (1024 SIMDs), 4..64 columns a wave
+        // 2..8 columns a wave, fewer when the grid gives under ~8 waves per
+        // SIMD (1024 SIMDs): on the 4096 x 4096 grid 8 columns (8704 FP32,
+        // 17920 FP64 waves) beat both shorter marches (more warm-up columns)
+        // and longer ones (fewer waves in flight)
         const int64_t want = 8192;
         int64_t x = nx * L.nstrips / want;
-        xch = (int)(x < 4 ? 4 : (x > 64 ? 64 : x));
+        xch = (int)(x < 2 ? 2 : (x > 8 ? 8 : x));
     }
     if (xch > nx)
         xch = (int)nx;
@@ -576,19 +591,19 @@ hipError_t launch_prep2d(const Run2D *dev, const Run2D &h, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_step2d(const Run2D *dev, const Run2D &h, const Launch2D &L, int64_t n,
-                         int par, hipStream_t s)
+hipError_t launch_step2d(const Run2D &h, const Launch2D &L, int64_t n, int par,
+                         hipStream_t s)
 {
     if (h.precision == GFDTD_F32) {
         if (L.C == 4)
-            return step_as<float, 4>(dev, h, L, n, par, s);
+            return step_as<float, 4>(h, L, n, par, s);
         if (L.C == 8)
-            return step_as<float, 8>(dev, h, L, n, par, s);
+            return step_as<float, 8>(h, L, n, par, s);
     } else {
         if (L.C == 2)
-            return step_as<double, 2>(dev, h, L, n, par, s);
+            return step_as<double, 2>(h, L, n, par, s);
         if (L.C == 4)
-            return step_as<double, 4>(dev, h, L, n, par, s);
+            return step_as<double, 4>(h, L, n, par, s);
     }
     return hipErrorInvalidValue;
 }

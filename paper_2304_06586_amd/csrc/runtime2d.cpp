@@ -447,7 +447,7 @@ gfdtd_status run_pass2d(gfdtd2d_run *r)
     if ((e = hipEventRecord(r->ev[1], r->stream)))
         return hip_fail(e, "event");
     for (int64_t n = 1; n <= r->steps; ++n)
-        if ((e = launch_step2d(dev, r->host, r->launch, n, (int)((n - 1) & 1), r->stream)))
+        if ((e = launch_step2d(r->host, r->launch, n, (int)((n - 1) & 1), r->stream)))
             return hip_fail(e, "2D step launch");
     if ((e = hipEventRecord(r->ev[2], r->stream)))
         return hip_fail(e, "event");

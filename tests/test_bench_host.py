@@ -79,6 +79,34 @@ class _FakeServer:
         return {"status": 0}
 
 
+def test_2d_roofline_and_its_counters(tmp_path, monkeypatch):
+    """The 2D kernel's roofline: algorithmic 6 words per cell-update over
+    the average launch; measured traffic only from counters taken on the
+    same kernel source and tiling."""
+    import hashlib
+    import workloads as W
+    sha = hashlib.sha256(open(bench.KERNEL2D_SRC, "rb").read()).hexdigest()
+    prof = tmp_path / "c2d.txt"
+    prof.write_text(f"kernel_source_sha256: {sha}\ncells_per_lane: 4\ncolumns_per_wave: 8\n"
+                    "fetch_bytes_per_update: 14.5\nwrite_bytes_per_update: 12.0\n")
+    monkeypatch.setitem(bench.COUNTERS_2D, (W.TE, W.F32), str(prof))
+    st = {"launches": 100, "step_ms": 10.0, "cell_updates": 100 * 2.0e7,
+          "cells_per_lane": 4, "columns_per_wave": 8, "waves": 1000}
+    r = bench.kernel_roofline_2d(st, W.TE, W.F32)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s"
+    assert abs(r["achieved"] - 2.0e7 * 24 / 1e-4 / 1e9) < 0.1      # 4800 GB/s
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+    assert abs(r["traffic"] - 26.5 * 2.0e7) < 1.0
+    st["columns_per_wave"] = 16
+    assert bench.kernel_roofline_2d(st, W.TE, W.F32)["traffic"] is None
+    assert bench.kernel_roofline_2d(st, W.TM, W.F32)["traffic"] is None
+    other = tmp_path / "kernels2d.hip"
+    other.write_text("// not the profiled source\n")
+    monkeypatch.setattr(bench, "KERNEL2D_SRC", str(other))
+    st["columns_per_wave"] = 8
+    assert bench.kernel_roofline_2d(st, W.TE, W.F32)["traffic"] is None
+
+
 def test_serving_driver_counts_latency_and_queueing(monkeypatch):
     clock = {"t": 0.0}
     monkeypatch.setattr(bench.time, "perf_counter", lambda: clock["t"])

@@ -102,6 +102,17 @@ def test_initial_state_on_a_ring(P, pol, beta):
     compare(P.gfdtd2d_solve(p), stepper2d.solve(p), TOL64, f"init ring {pol} {beta}")
 
 
+@pytest.mark.parametrize("pol", [W.TE, W.TM])
+@pytest.mark.parametrize("nz,abc", [(40, W.ABC_PERIODIC), (16, W.ABC_MUR1)])
+def test_profile_moves_beyond_the_grid(P, pol, nz, abc):
+    """Long runs on short grids: the profile shift m = rint(beta S tau)
+    passes several grid lengths (wrapped on a ring, clamped off it)."""
+    p = W.small_case_2d(7, nz, 1500, 0.5, pol=pol, abc=abc, seed=9, structure="random")
+    m_end = round(p.beta * p.courant * (p.steps + 0.5))
+    assert m_end > 4 * nz
+    compare(P.gfdtd2d_solve(p), stepper2d.solve(p), TOL64, f"long shift {pol} {nz} {abc}")
+
+
 def test_zero_steps_return_the_initial_state(P):
     rng = np.random.default_rng(1)
     p = W.small_case_2d(9, 80, 0, 0.2, pol=W.TM)
