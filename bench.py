@@ -111,7 +111,7 @@ def measured_traffic_per_update(C, T, precision=W.F32):
         return None
 
 
-def measured_traffic_2d(pol, precision, C, xch):
+def measured_traffic_2d(pol, precision, C, xch, T=1):
     """HBM bytes per cell-update of k_step2d from committed rocprofv3
     FETCH_SIZE/WRITE_SIZE counters (copy-calibrated), or None when there
     are none for this polarization and precision, the kernel source has
@@ -129,7 +129,8 @@ def measured_traffic_2d(pol, precision, C, xch):
         sha = hashlib.sha256(open(KERNEL2D_SRC, "rb").read()).hexdigest()
         if kv.get("kernel_source_sha256") != sha:
             return None
-        if int(kv["cells_per_lane"]) != C or int(kv["columns_per_wave"]) != xch:
+        if (int(kv["cells_per_lane"]) != C or int(kv["columns_per_wave"]) != xch
+                or int(kv.get("block_steps", 1)) != T):
             return None
         return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
     except (OSError, KeyError, ValueError):
@@ -137,16 +138,21 @@ def measured_traffic_2d(pol, precision, C, xch):
 
 
 def kernel_roofline_2d(st, pol, precision):
-    """k_step2d of the last pass against the HBM peak: algorithmic bytes per
-    launch (6 words per cell-update) over the average launch time from the
-    library's HIP events around the pass's stepping launches."""
+    """k_step2d of the last pass against the HBM peak.  A launch of T steps
+    reads and writes D, B and C of every cell once: algorithmic bytes per
+    launch are 6 words a cell (24 B FP32, 48 B FP64), i.e. 6/T words per
+    cell-update, over the average launch time from the library's HIP
+    events around the pass's stepping launches.  The single-step figure
+    (6 words per cell-update, what the same rate would need without
+    temporal blocking) is given beside it."""
     launches = max(1, int(st["launches"]))
     avg_launch_ms = st["step_ms"] / launches
     upd_per_launch = st["cell_updates"] / launches
-    alg = upd_per_launch * BYTES_PER_UPDATE_2D[precision]
+    T = max(1, int(st.get("block_steps", 1)))
+    alg = upd_per_launch * BYTES_PER_UPDATE_2D[precision] / T
     achieved = alg / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
     per_update = measured_traffic_2d(pol, precision, int(st["cells_per_lane"]),
-                                     int(st["columns_per_wave"]))
+                                     int(st["columns_per_wave"]), T)
     traffic = per_update * upd_per_launch if per_update is not None else None
     return {
         "kernel": "k_step2d",
@@ -159,7 +165,12 @@ def kernel_roofline_2d(st, pol, precision):
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                         "copy-calibrated)",
         "algorithmic_bytes_per_launch": alg,
-        "bytes_per_update": BYTES_PER_UPDATE_2D[precision],
+        "bytes_per_update": BYTES_PER_UPDATE_2D[precision] / T,
+        "single_step_hbm_equiv_GBs": (round(alg * T / (avg_launch_ms * 1e-3) / 1e9, 1)
+                                      if avg_launch_ms > 0 else 0.0),
+        "block_steps": T,
+        "kernel_cell_updates_per_s": (st["cell_updates"] / (st["step_ms"] * 1e-3)
+                                      if st["step_ms"] > 0 else 0.0),
         "launches_per_pass": launches,
         "avg_launch_ms": round(avg_launch_ms, 4),
         "cells_per_lane": int(st["cells_per_lane"]),
@@ -199,7 +210,8 @@ def twod_leg(P, args):
                 "roofline": kernel_roofline_2d(st, pol, prec)}
             log(f"2d {pname}_{dname}: {p.cell_updates / dt:.4g} cell-updates/s, "
                 f"{dt * 1e3:.1f} ms, k_step2d {out[f'{pname}_{dname}']['roofline']['achieved']}"
-                f" GB/s (C={st['cells_per_lane']}, {st['columns_per_wave']} columns/wave)")
+                f" GB/s (C={st['cells_per_lane']}, {st['columns_per_wave']} columns/wave, "
+                f"T={st['block_steps']})")
     for pname in ("te", "tm"):
         if (pname, "f64") not in full or (pname, "f32") not in full:
             continue

@@ -146,15 +146,19 @@ gfdtd_status gfdtd2d_workspace_bytes(const gfdtd2d_problem *p, int64_t steps,
 
 /*
  * Execution options (NULL = automatic).  cells_per_lane: z cells a lane
- * holds (FP32: 4 or 8, FP64: 2 or 4; 0 = auto); columns_per_wave: columns
- * a wave steps in one launch (0 = auto).  Results do not depend on them
- * (bit for bit).
+ * holds (FP32: 2, 4 or 8, FP64: 2 or 4; 0 = auto); columns_per_wave:
+ * columns a wave steps in one launch (0 = auto); block_steps: steps a
+ * launch advances the grid, 1, 2 or 4 (0 = auto); more than 1 needs the
+ * narrow lanes (FP32 at most 4 cells, FP64 2) and ends other than
+ * periodic.  A run whose
+ * step count is not a multiple finishes with one-step launches.  Results
+ * do not depend on these options (bit for bit).
  */
 typedef struct gfdtd2d_exec {
     uint32_t struct_size;
     int32_t cells_per_lane;
     int32_t columns_per_wave;
-    int32_t reserved0;
+    int32_t block_steps;
 } gfdtd2d_exec;
 
 typedef struct gfdtd2d_run gfdtd2d_run;
@@ -185,6 +189,9 @@ typedef struct gfdtd2d_stats {
     double step_ms;              /* device time of the last pass's stepping
                                     launches (HIP events on the stream)    */
     double pass_ms;              /* device time of the whole last pass     */
+    int32_t block_steps;         /* steps per launch (the last launches of
+                                    a pass may take one)                   */
+    int32_t reserved0;
 } gfdtd2d_stats;
 
 gfdtd_status gfdtd2d_get_stats(const gfdtd2d_run *r, gfdtd2d_stats *s);

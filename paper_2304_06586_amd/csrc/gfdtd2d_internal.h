@@ -30,17 +30,17 @@ struct Run2D {
 };
 
 // Launch geometry of the stepping kernel: a wave holds 64 * C rows of a
-// z-strip (HALO2D rows on each side are recomputed, not stored) and steps
-// `xch` consecutive columns.
-constexpr int HALO2D = 4;
+// z-strip (halo rows on each side are recomputed, not stored) and advances
+// `xch` consecutive columns by T steps (T in {1, 2, 4}).
 struct Launch2D {
     int C = 4;
     int xch = 16;
+    int T = 1;
     int64_t nstrips = 0, nchunks = 0, waves = 0, blocks = 0;
 };
 
-int64_t strip_rows(int C);
-Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch);
+int64_t strip_rows(int C, int T);
+Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch, int T);
 
 hipError_t launch_prep2d(const Run2D *dev, const Run2D &host, hipStream_t s);
 // One stepping launch; the descriptor travels by value as a kernel argument.

@@ -24,6 +24,14 @@
 // computed but not stored).  Blocks of 4 waves are numbered so that each
 // XCD takes a contiguous range of strips.
 //
+// Temporal blocking: a launch may advance the grid by T steps (T = 2 or 4
+// off a z-ring).  The march then runs T stages, stage t one column behind
+// stage t - 1 and taking its input fields from registers, so a cell-update
+// moves 6/T words through HBM plus the warm-up columns; strips overlap by
+// 3T rows a side (rounded up to a multiple of 4), and between stages the
+// rows off the grid take the fields' edge values again, as the step reads
+// them.
+//
 // Arithmetic follows the oracle's order of operations per term (division
 // by eps, mu replaced by a multiply with the reciprocal), with floating-point
 // contraction off in this file: every cell-update is the same sequence of
@@ -32,6 +40,8 @@
 // rounding.
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "gfdtd.h"
 #include "gfdtd2d.h"
@@ -108,9 +118,13 @@ __device__ __forceinline__ void next1(const R (&a)[C], R (&o)[C])
     o[C - 1] = lane_right(a[0]);
 }
 
-template <typename R> struct Vec16;
-template <> struct Vec16<float> { using T = float4; };
-template <> struct Vec16<double> { using T = double2; };
+// The vector type of one lane's C rows: 16 bytes (float4, double2), or 8
+// for two FP32 rows (float2).
+template <typename R, int C> struct RowVec;
+template <int C> struct RowVec<float, C> {
+    using T = typename std::conditional<C % 4 == 0, float4, float2>::type;
+};
+template <int C> struct RowVec<double, C> { using T = double2; };
 
 __device__ __forceinline__ int clampi(int i, int lo, int hi)
 {
@@ -123,21 +137,21 @@ __device__ __forceinline__ int wrapi(int i, int n)
     return r < 0 ? r + n : r;
 }
 
-// Rows r0..r0+C-1 of a column whose lattice has n nodes: one 16-byte load
-// per 16 bytes when they all lie on the lattice, else per row with the
-// edge value off the grid (wrapped on a z-ring).
+// Rows r0..r0+C-1 of a column whose lattice has n nodes: vector loads
+// when they all lie on the lattice, else per row with the edge value off
+// the grid (wrapped on a z-ring).
 template <typename R, int C>
 __device__ __forceinline__ void load_rows(const R *__restrict__ col, int r0, int n, int nz,
                                           bool ring, R (&a)[C])
 {
     if (r0 >= 0 && r0 + C <= n) {
-        using V = typename Vec16<R>::T;
-        constexpr int U = 16 / sizeof(R);
+        using V = typename RowVec<R, C>::T;
+        constexpr int U = sizeof(V) / sizeof(R);
         const V *p = reinterpret_cast<const V *>(col + r0);
 #pragma unroll
         for (int u = 0; u < C / U; ++u) {
             const V v = p[u];
-            __builtin_memcpy(&a[u * U], &v, 16);
+            __builtin_memcpy(&a[u * U], &v, sizeof(V));
         }
     } else {
 #pragma unroll
@@ -154,13 +168,13 @@ __device__ __forceinline__ void store_rows(R *__restrict__ col, int r0, int lo, 
                                            const R (&a)[C])
 {
     if (r0 >= lo && r0 + C <= hi) {
-        using V = typename Vec16<R>::T;
-        constexpr int U = 16 / sizeof(R);
+        using V = typename RowVec<R, C>::T;
+        constexpr int U = sizeof(V) / sizeof(R);
         V *p = reinterpret_cast<V *>(col + r0);
 #pragma unroll
         for (int u = 0; u < C / U; ++u) {
             V v;
-            __builtin_memcpy(&v, &a[u * U], 16);
+            __builtin_memcpy(&v, &a[u * U], sizeof(V));
             p[u] = v;
         }
     } else {
@@ -193,8 +207,33 @@ __device__ __forceinline__ int shift_at(double bS, double tau, int nz, bool ring
     return (int)(m > lim ? lim : (m < -lim ? -lim : m));
 }
 
-template <typename R, int C, bool TE, bool COLA>
-__global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int par, int xch,
+__device__ __forceinline__ float readlane_r(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ double readlane_r(double v, int l)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Halo rows of a strip for T steps a launch: a step reaches 3 rows upwind
+// and 2 downwind, so 3T on each side, rounded up to a multiple of 4 (which
+// keeps every lane's rows 16-byte aligned).
+constexpr int halo_rows(int T) { return (3 * T + 3) / 4 * 4; }
+
+// The step kernel.  T steps a launch (T = 1 on a z-ring): the march along
+// x runs T stages, stage t performing step n0 + t one column behind stage
+// t - 1, whose new fields it takes from registers; only the last stage
+// stores.  Stage t at column j needs stage t - 1's fields up to column
+// j + 1, and every stage needs two columns before its first valid one
+// (its carried E*/H* terms), so the march starts T + 1 columns before the
+// chunk and runs T - 1 columns past it.
+template <typename R, int C, bool TE, bool COLA, int T>
+__global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int par, int xch,
                                                 int nstrips, int waves, int blocks)
 {
     const int lane = threadIdx.x & 63;
@@ -204,7 +243,8 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
     const int w = lb * 4 + (int)(threadIdx.x >> 6);
     if (w >= waves)
         return;
-    constexpr int STRIDE = 64 * C - 2 * HALO2D;
+    constexpr int H = halo_rows(T);
+    constexpr int STRIDE = 64 * C - 2 * H;
     const int s = w % nstrips;
     const int chunk = w / nstrips;
     const int nx = (int)rd.nx, nz = (int)rd.nz, nh = (int)rd.nh, nc = (int)rd.nc;
@@ -212,27 +252,54 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
     const bool ring = rd.abc == GFDTD_ABC_PERIODIC;
     const int vlo = s * STRIDE;
     const int vhi = vlo + STRIDE < nz ? vlo + STRIDE : nz;
-    const int r0 = vlo - HALO2D + lane * C;
+    const int z0 = vlo - H;                  // first row the wave holds
+    const int r0 = z0 + lane * C;
     const int i0 = chunk * xch;
     const int i1 = i0 + xch < nx ? i0 + xch : nx;
 
     const double Sd = rd.S, betad = rd.beta, bSd = betad * Sd;
     const R S = (R)Sd, beta = (R)betad, bS = (R)bSd, half = (R)0.5;
-    const int mEp = shift_at(bSd, (double)n - 0.5, nz, ring);   // E* of step n-1
-    const int mH = shift_at(bSd, (double)n, nz, ring);
-    const int mE = shift_at(bSd, (double)n + 0.5, nz, ring);
 
-    // per-row material coefficients (z only)
-    R ce[C], chB[C], cc[C];
+    // the rows a wave holds that need the source, the ends or the grid-edge
+    // values (halo rows included: later stages read them)
+    const int src_row = (int)rd.src_row;
+    const bool src_here = src_row >= z0 && src_row < z0 + 64 * C;
+    const bool lo_edge = !ring && z0 < 0;
+    const bool hi_edge_d = !ring && z0 + 64 * C > nz - 1;
+
+    // per-stage constants: material coefficients (z only), source sample,
+    // end coefficients, the shift for the probes' eps
+    R ce[T][C], chB[T][C], cc[T][C];
+    double gs[T];
+    R cLs[T], cRs[T];
+    int mEs[T];
 #pragma unroll
-    for (int q = 0; q < C; ++q) {
-        const int r = r0 + q;
-        ce[q] = (R)(1.0 / rd.eps[rest_cell(r, mEp, nz - 1, nz, ring)]);
-        chB[q] = (R)(1.0 / rd.mu[rest_cell(r, mH, ring ? nz - 1 : nz - 2, nz, ring)]);
-        if (TE)   // B_z at (i+1/2, k): mu cell k
-            cc[q] = (R)(1.0 / rd.mu[rest_cell(r, mH, nz - 1, nz, ring)]);
-        else      // D_z at (i, j+1/2): eps cell j+1
-            cc[q] = (R)(1.0 / rd.eps[rest_cell(r + 1, mEp, nz - 1, nz, ring)]);
+    for (int st = 0; st < T; ++st) {
+        const int64_t n = n0 + st;
+        const int mEp = shift_at(bSd, (double)n - 0.5, nz, ring);   // E* of step n-1
+        const int mH = shift_at(bSd, (double)n, nz, ring);
+        const int mE = shift_at(bSd, (double)n + 0.5, nz, ring);
+        mEs[st] = mE;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int r = r0 + q;
+            ce[st][q] = (R)(1.0 / rd.eps[rest_cell(r, mEp, nz - 1, nz, ring)]);
+            chB[st][q] = (R)(1.0 / rd.mu[rest_cell(r, mH, ring ? nz - 1 : nz - 2, nz, ring)]);
+            if (TE)   // B_z at (i+1/2, k): mu cell k
+                cc[st][q] = (R)(1.0 / rd.mu[rest_cell(r, mH, nz - 1, nz, ring)]);
+            else      // D_z at (i, j+1/2): eps cell j+1
+                cc[st][q] = (R)(1.0 / rd.eps[rest_cell(r + 1, mEp, nz - 1, nz, ring)]);
+        }
+        gs[st] = (src_here && n <= rd.nsrc) ? rd.src[n - 1] : 0.0;
+        cLs[st] = cRs[st] = (R)0;
+        if (rd.abc == GFDTD_ABC_MUR1 && (lo_edge || hi_edge_d)) {
+            const double nL = sqrt(rd.eps[clampi(-mE, 0, nz - 1)] * rd.mu[clampi(-mE, 0, nz - 2)]);
+            const double nR = sqrt(rd.eps[clampi(nz - 1 - mE, 0, nz - 1)] *
+                                   rd.mu[clampi(nz - 2 - mE, 0, nz - 2)]);
+            const double uL = 1.0 / nL, uR = 1.0 / nR;
+            cLs[st] = (R)((Sd * uL - 1.0) / (Sd * uL + 1.0));
+            cRs[st] = (R)((Sd * uR - 1.0) / (Sd * uR + 1.0));
+        }
     }
 
     const R *Din = static_cast<const R *>(par ? rd.f[1] : rd.f[0]);
@@ -241,28 +308,18 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
     R *Dout = static_cast<R *>(par ? rd.f[0] : rd.f[1]);
     R *Bout = static_cast<R *>(par ? rd.f[2] : rd.f[3]);
     R *Cout = static_cast<R *>(par ? rd.f[4] : rd.f[5]);
-    // column i (i0 - 1 <= i <= i1 + 1) wrapped onto 0..nx-1
-    auto colp = [&](const R *base, int i) {
-        const int iw = nx == 1 ? 0 : (i < 0 ? i + nx : (i >= nx ? i - nx : i));
-        return base + (int64_t)iw * ld;
+    // column i (i0 - T - 1 <= i <= i1 + T - 1) wrapped onto 0..nx-1: one
+    // conditional add or subtract once nx exceeds the march's overhang
+    auto wrapc = [&](int i) {
+        if (nx <= 2 * T + 2) {
+            const int r = i % nx;
+            return r < 0 ? r + nx : r;
+        }
+        return i < 0 ? i + nx : (i >= nx ? i - nx : i);
     };
+    auto colp = [&](const R *base, int i) { return base + (int64_t)wrapc(i) * ld; };
 
-    // step-wide scalars: source sample, end coefficients, probes of this wave
-    const int src_row = (int)rd.src_row;
-    const bool has_src = n <= rd.nsrc && src_row >= vlo && src_row < vhi;
-    const double g = has_src ? rd.src[n - 1] : 0.0;
-    const bool left_end = !ring && vlo == 0;
-    const bool right_end = !ring && vhi == nz;
-    R cL = 0, cR = 0;
-    if (rd.abc == GFDTD_ABC_MUR1 && (left_end || right_end)) {
-        const double nL = sqrt(rd.eps[clampi(-mE, 0, nz - 1)] * rd.mu[clampi(-mE, 0, nz - 2)]);
-        const double nR = sqrt(rd.eps[clampi(nz - 1 - mE, 0, nz - 1)] *
-                               rd.mu[clampi(nz - 2 - mE, 0, nz - 2)]);
-        const double uL = 1.0 / nL, uR = 1.0 / nR;
-        cL = (R)((Sd * uL - 1.0) / (Sd * uL + 1.0));
-        cR = (R)((Sd * uR - 1.0) / (Sd * uR + 1.0));
-    }
-    uint64_t own = 0;
+    uint64_t own = 0;                        // probes this wave records
     for (int q = 0; q < rd.nprobe; ++q) {
         const int64_t x = rd.px[q], z = rd.pz[q];
         if (z >= vlo && z < vhi && x >= i0 && x < i1)
@@ -270,7 +327,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
     }
 
     // E* = D/eps +- beta * (Table 1 B average), TE +, TM -
-    auto star_e = [&](const R (&D)[C], const R (&B)[C], R (&E)[C]) {
+    auto star_e = [&](const R (&cE)[C], const R (&D)[C], const R (&B)[C], R (&E)[C]) {
         R a1[C], a2[C];
         if (COLA) {
             prev1<R, C>(B, a1);
@@ -284,7 +341,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
 #pragma unroll
         for (int q = 0; q < C; ++q) {
             const R bb = half * (a1[q] + a2[q]);
-            E[q] = TE ? D[q] * ce[q] + beta * bb : D[q] * ce[q] - beta * bb;
+            E[q] = TE ? D[q] * cE[q] + beta * bb : D[q] * cE[q] - beta * bb;
         }
     };
     // Table 1 upwind z-difference: F - F(r-1) (v >= 0) or F(r+1) - F (v < 0)
@@ -302,47 +359,48 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
                 d[q] = t[q] - F[q];
         }
     };
-    // source, z ends and probes on the new D of column i, then store
-    auto finish_d = [&](int i, const R (&Dold)[C], R (&Dn)[C]) {
-        if (has_src) {
-            const double add = rd.prof[i] * g;
+    // source, z ends and probes on the new D of column j at stage st
+    auto finish_d = [&](int st, int j, const R (&Dold)[C], R (&Dn)[C]) {
+        const int64_t n = n0 + st;
+        if (src_here && n <= rd.nsrc) {
+            const double add = rd.prof[wrapc(j)] * gs[st];
 #pragma unroll
             for (int q = 0; q < C; ++q)
                 if (r0 + q == src_row)
                     Dn[q] = (R)((double)Dn[q] + add);
         }
         if (rd.abc == GFDTD_ABC_MUR1) {
-            if (left_end) {          // D'(0) = D(1) + cL (D'(1) - D(0))
+            if (lo_edge) {           // D'(0) = D(1) + cL (D'(1) - D(0))
                 R dn1[C], do1[C];
                 next1<R, C>(Dn, dn1);
                 next1<R, C>(Dold, do1);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
                     if (r0 + q == 0)
-                        Dn[q] = do1[q] + cL * (dn1[q] - Dold[q]);
+                        Dn[q] = do1[q] + cLs[st] * (dn1[q] - Dold[q]);
             }
-            if (right_end) {         // D'(nz-1) = D(nz-2) + cR (D'(nz-2) - D(nz-1))
+            if (hi_edge_d) {         // D'(nz-1) = D(nz-2) + cR (D'(nz-2) - D(nz-1))
                 R dm1[C], om1[C];
                 prev1<R, C>(Dn, dm1);
                 prev1<R, C>(Dold, om1);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
                     if (r0 + q == nz - 1)
-                        Dn[q] = om1[q] + cR * (dm1[q] - Dold[q]);
+                        Dn[q] = om1[q] + cRs[st] * (dm1[q] - Dold[q]);
             }
-        } else if (rd.abc == GFDTD_ABC_PEC && (left_end || right_end)) {
+        } else if (rd.abc == GFDTD_ABC_PEC && (lo_edge || hi_edge_d)) {
 #pragma unroll
             for (int q = 0; q < C; ++q)
                 if (r0 + q == 0 || r0 + q == nz - 1)
                     Dn[q] = (R)0;
         }
-        if (own) {
+        if (own && j >= i0 && j < i1) {
             for (uint64_t m = own; m; m &= m - 1) {
                 const int q = __builtin_ctzll(m);
-                if (rd.px[q] != i)
+                if (rd.px[q] != j)
                     continue;
                 const int z = (int)rd.pz[q];
-                const int off = z - (vlo - HALO2D);
+                const int off = z - z0;
                 const int lp = off / C, qq = off % C;
                 R v = Dn[0];
 #pragma unroll
@@ -351,153 +409,188 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n, int p
                         v = Dn[t];
                 if (lane == lp)
                     rd.trace[(int64_t)q * rd.steps + (n - 1)] =
-                        (double)v / rd.eps[rest_cell(z, mE, nz - 1, nz, ring)];
+                        (double)v / rd.eps[rest_cell(z, mEs[st], nz - 1, nz, ring)];
             }
         }
     };
+    // Off-lattice rows of a stage's new field (rows < 0 or >= nlat) take the
+    // edge values of that field, as the step reads them (grid ends only).
+    auto edge_values = [&](R (&a)[C], int nlat) {
+        if (lo_edge) {
+            constexpr int L0 = H / C, Q0 = H % C;     // row 0 of strip 0
+            const R e = readlane_r(a[Q0], L0);
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if (r0 + q < 0)
+                    a[q] = e;
+        }
+        if (!ring && z0 + 64 * C > nlat) {
+            const int off = nlat - 1 - z0;
+            const int lr = off / C, qr = off % C;
+            R v = a[0];
+#pragma unroll
+            for (int t = 1; t < C; ++t)
+                if (t == qr)
+                    v = a[t];
+            const R e = readlane_r(v, lr);
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if (r0 + q >= nlat)
+                    a[q] = e;
+        }
+    };
 
-    R dd[C], t1[C], t2[C];
-    if (TE) {
-        // prologue and warm-up column i0-1: E*(i0-1), E*(i0), Hc(i0-1)
-        R Dc[C], Bc[C], Ep[C], Hcp[C], Cc[C];
-        load_rows<R, C>(colp(Din, i0 - 1), r0, nz, nz, ring, Dc);
-        load_rows<R, C>(colp(Bin, i0 - 1), r0, nh, nz, ring, Bc);
-        star_e(Dc, Bc, Ep);
-        load_rows<R, C>(colp(Din, i0), r0, nz, nz, ring, Dc);
-        load_rows<R, C>(colp(Bin, i0), r0, nh, nz, ring, Bc);
-        load_rows<R, C>(colp(Cin, i0 - 1), r0, nc, nz, ring, Cc);
-        {
-            R En[C];
-            star_e(Dc, Bc, En);
-            dz_up(Cc, dd);
+    // carried state per stage (zero until the stage's warm-up columns set it)
+    R k1[T][C], k2[T][C], k3[T][C], k4[T][C];   // TE: D, B, E*, H*_z; TM: C, E*_z, H*_y
+    R dl[T][C], dl2[T][C];                       // TE: delayed C; TM: delayed D, B
 #pragma unroll
-            for (int q = 0; q < C; ++q)
-                Hcp[q] = (Cc[q] - S * (En[q] - Ep[q]) - bS * dd[q]) * cc[q];
-#pragma unroll
-            for (int q = 0; q < C; ++q)
-                Ep[q] = En[q];
-        }
-        // loads of the first column
-        R Dl[C], Bl[C], Cl[C];
-        load_rows<R, C>(colp(Din, i0 + 1), r0, nz, nz, ring, Dl);
-        load_rows<R, C>(colp(Bin, i0 + 1), r0, nh, nz, ring, Bl);
-        load_rows<R, C>(colp(Cin, i0), r0, nc, nz, ring, Cl);
-        for (int i = i0; i < i1; ++i) {
-            R Dx[C], Bx[C];
-#pragma unroll
-            for (int q = 0; q < C; ++q) {
-                Dx[q] = Dl[q];
-                Bx[q] = Bl[q];
-                Cc[q] = Cl[q];
-            }
-            if (i + 1 < i1) {        // next column's loads, in flight meanwhile
-                load_rows<R, C>(colp(Din, i + 2), r0, nz, nz, ring, Dl);
-                load_rows<R, C>(colp(Bin, i + 2), r0, nh, nz, ring, Bl);
-                load_rows<R, C>(colp(Cin, i + 1), r0, nc, nz, ring, Cl);
-            }
-            R En[C], Bn[C], Cn[C], Hs[C], Hc[C], Dn[C];
-            star_e(Dx, Bx, En);
-            // (10a): B_x^n and B_z^n
-            next1<R, C>(Ep, t1);
-            dz_up(Bc, dd);
-#pragma unroll
-            for (int q = 0; q < C; ++q)
-                Bn[q] = Bc[q] + S * (t1[q] - Ep[q]) - bS * dd[q];
-            dz_up(Cc, dd);
-#pragma unroll
-            for (int q = 0; q < C; ++q)
-                Cn[q] = Cc[q] - S * (En[q] - Ep[q]) - bS * dd[q];
-            // (10d): H*_x = B_x/mu + beta Dbar, H*_z = B_z/mu
-            next1<R, C>(Dc, t1);
-#pragma unroll
-            for (int q = 0; q < C; ++q) {
-                Hs[q] = Bn[q] * chB[q] + beta * (half * (t1[q] + Dc[q]));
-                Hc[q] = Cn[q] * cc[q];
-            }
-            // (10b): D_y^{n+1/2}
-            prev1<R, C>(Hs, t2);
-            dz_up(Dc, dd);
-#pragma unroll
-            for (int q = 0; q < C; ++q)
-                Dn[q] = Dc[q] + S * (Hs[q] - t2[q]) - S * (Hc[q] - Hcp[q]) - bS * dd[q];
-            finish_d(i, Dc, Dn);
-            const int64_t o = (int64_t)i * ld;
-            store_rows<R, C>(Dout + o, r0, vlo, vhi, Dn);
-            store_rows<R, C>(Bout + o, r0, vlo, vhi < nh ? vhi : nh, Bn);
-            store_rows<R, C>(Cout + o, r0, vlo, vhi < nc ? vhi : nc, Cn);
-#pragma unroll
-            for (int q = 0; q < C; ++q) {
-                Hcp[q] = Hc[q];
-                Ep[q] = En[q];
-                Dc[q] = Dx[q];
-                Bc[q] = Bx[q];
-            }
-        }
-    } else {
-        // prologue: E*_z(i0-1); warm-up column i0-1 gives H*_y(i0-1)
-        R Cr[C], Ecp[C], Hsp[C];
-        load_rows<R, C>(colp(Cin, i0 - 1), r0, nc, nz, ring, Cr);
+    for (int st = 0; st < T; ++st)
 #pragma unroll
         for (int q = 0; q < C; ++q)
-            Ecp[q] = Cr[q] * cc[q];
-        R Dl[C], Bl[C], Cl[C];
-        load_rows<R, C>(colp(Din, i0 - 1), r0, nz, nz, ring, Dl);
-        load_rows<R, C>(colp(Bin, i0 - 1), r0, nh, nz, ring, Bl);
-        load_rows<R, C>(colp(Cin, i0), r0, nc, nz, ring, Cl);
-        for (int i = i0 - 1; i < i1; ++i) {
-            R Dc[C], Bc[C], Cx[C];
+            k1[st][q] = k2[st][q] = k3[st][q] = k4[st][q] = dl[st][q] = dl2[st][q] = (R)0;
+
+    const int kbeg = i0 - T - 1, kend = i1 + T - 2;   // stage 0's columns
+    // loads of stage 0's first column: TE D, B at k + 1 and C at k; TM D, B
+    // at k and C at k + 1
+    R Ld[C], Lb[C], Lc[C];
+    load_rows<R, C>(colp(Din, TE ? kbeg + 1 : kbeg), r0, nz, nz, ring, Ld);
+    load_rows<R, C>(colp(Bin, TE ? kbeg + 1 : kbeg), r0, nh, nz, ring, Lb);
+    load_rows<R, C>(colp(Cin, TE ? kbeg : kbeg + 1), r0, nc, nz, ring, Lc);
+    R dd[C], t1[C], t2[C];
+    for (int k = kbeg; k <= kend; ++k) {
+        R inD[C], inB[C], inC[C];
 #pragma unroll
-            for (int q = 0; q < C; ++q) {
-                Dc[q] = Dl[q];
-                Bc[q] = Bl[q];
-                Cx[q] = Cl[q];
-            }
-            if (i + 1 < i1) {
-                load_rows<R, C>(colp(Din, i + 1), r0, nz, nz, ring, Dl);
-                load_rows<R, C>(colp(Bin, i + 1), r0, nh, nz, ring, Bl);
-                load_rows<R, C>(colp(Cin, i + 2), r0, nc, nz, ring, Cl);
-            }
-            R Es[C], Ecn[C], Bn[C], Hs[C];
-            star_e(Dc, Bc, Es);
+        for (int q = 0; q < C; ++q) {
+            inD[q] = Ld[q];
+            inB[q] = Lb[q];
+            inC[q] = Lc[q];
+        }
+        if (k < kend) {            // next column's loads, in flight meanwhile
+            const int kn = k + 1;
+            load_rows<R, C>(colp(Din, TE ? kn + 1 : kn), r0, nz, nz, ring, Ld);
+            load_rows<R, C>(colp(Bin, TE ? kn + 1 : kn), r0, nh, nz, ring, Lb);
+            load_rows<R, C>(colp(Cin, TE ? kn : kn + 1), r0, nc, nz, ring, Lc);
+        }
+        R nxt[T][C], nxt2[T][C];   // delayed inputs for the next column
 #pragma unroll
-            for (int q = 0; q < C; ++q)
-                Ecn[q] = Cx[q] * cc[q];
-            // (10a): B_y^n
-            next1<R, C>(Es, t1);
-            dz_up(Bc, dd);
+        for (int st = 0; st < T; ++st) {
+            const int j = k - st;                      // this stage's column
+            R oD[C], oB[C], oC[C];
+            if (TE) {
+                // inputs: D, B at column j + 1; C at column j
+                R Cj[C];
 #pragma unroll
-            for (int q = 0; q < C; ++q)
-                Bn[q] = Bc[q] - S * (t1[q] - Es[q]) + S * (Ecn[q] - Ecp[q]) - bS * dd[q];
-            // (10d): H*_y = B_y/mu - beta Dbar
-            next1<R, C>(Dc, t1);
+                for (int q = 0; q < C; ++q)
+                    Cj[q] = st == 0 ? inC[q] : dl[st][q];
+                R En[C], Hs[C], Hc[C];
+                star_e(ce[st], inD, inB, En);
+                // (10a): B_x^n and B_z^n
+                next1<R, C>(k3[st], t1);
+                dz_up(k2[st], dd);
 #pragma unroll
-            for (int q = 0; q < C; ++q)
-                Hs[q] = Bn[q] * chB[q] - beta * (half * (t1[q] + Dc[q]));
-            if (i >= i0) {
-                // (10b): D_x^{n+1/2} and D_z^{n+1/2}
-                R Dn[C], Cn[C];
+                for (int q = 0; q < C; ++q)
+                    oB[q] = k2[st][q] + S * (t1[q] - k3[st][q]) - bS * dd[q];
+                dz_up(Cj, dd);
+#pragma unroll
+                for (int q = 0; q < C; ++q)
+                    oC[q] = Cj[q] - S * (En[q] - k3[st][q]) - bS * dd[q];
+                // (10d): H*_x = B_x/mu + beta Dbar, H*_z = B_z/mu
+                next1<R, C>(k1[st], t1);
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    Hs[q] = oB[q] * chB[st][q] + beta * (half * (t1[q] + k1[st][q]));
+                    Hc[q] = oC[q] * cc[st][q];
+                }
+                // (10b): D_y^{n+1/2}
                 prev1<R, C>(Hs, t2);
-                dz_up(Dc, dd);
+                dz_up(k1[st], dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    Dn[q] = Dc[q] - S * (Hs[q] - t2[q]) - bS * dd[q];
-                dz_up(Cr, dd);
+                    oD[q] = k1[st][q] + S * (Hs[q] - t2[q]) - S * (Hc[q] - k4[st][q]) -
+                            bS * dd[q];
+                finish_d(st, j, k1[st], oD);
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    k4[st][q] = Hc[q];
+                    k3[st][q] = En[q];
+                    k1[st][q] = inD[q];
+                    k2[st][q] = inB[q];
+                }
+            } else {
+                // inputs: D, B at column j; C at column j + 1
+                R Dj[C], Bj[C];
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    Dj[q] = st == 0 ? inD[q] : dl[st][q];
+                    Bj[q] = st == 0 ? inB[q] : dl2[st][q];
+                }
+                R Es[C], Ecn[C], Hs[C];
+                star_e(ce[st], Dj, Bj, Es);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    Cn[q] = Cr[q] + S * (Hs[q] - Hsp[q]) - bS * dd[q];
-                finish_d(i, Dc, Dn);
-                const int64_t o = (int64_t)i * ld;
-                store_rows<R, C>(Dout + o, r0, vlo, vhi, Dn);
-                store_rows<R, C>(Bout + o, r0, vlo, vhi < nh ? vhi : nh, Bn);
-                store_rows<R, C>(Cout + o, r0, vlo, vhi < nc ? vhi : nc, Cn);
+                    Ecn[q] = inC[q] * cc[st][q];
+                // (10a): B_y^n
+                next1<R, C>(Es, t1);
+                dz_up(Bj, dd);
+#pragma unroll
+                for (int q = 0; q < C; ++q)
+                    oB[q] = Bj[q] - S * (t1[q] - Es[q]) + S * (Ecn[q] - k2[st][q]) - bS * dd[q];
+                // (10d): H*_y = B_y/mu - beta Dbar
+                next1<R, C>(Dj, t1);
+#pragma unroll
+                for (int q = 0; q < C; ++q)
+                    Hs[q] = oB[q] * chB[st][q] - beta * (half * (t1[q] + Dj[q]));
+                // (10b): D_x^{n+1/2} and D_z^{n+1/2}
+                prev1<R, C>(Hs, t2);
+                dz_up(Dj, dd);
+#pragma unroll
+                for (int q = 0; q < C; ++q)
+                    oD[q] = Dj[q] - S * (Hs[q] - t2[q]) - bS * dd[q];
+                dz_up(k1[st], dd);
+#pragma unroll
+                for (int q = 0; q < C; ++q)
+                    oC[q] = k1[st][q] + S * (Hs[q] - k3[st][q]) - bS * dd[q];
+                finish_d(st, j, Dj, oD);
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    k3[st][q] = Hs[q];
+                    k2[st][q] = Ecn[q];
+                    k1[st][q] = inC[q];
+                }
             }
+            if (st + 1 < T) {
+                // the next stage's inputs: its new fields, with the grid's
+                // edge values on off-lattice rows
+                edge_values(oD, nz);
+                edge_values(oB, nh);
+                edge_values(oC, nc);
 #pragma unroll
-            for (int q = 0; q < C; ++q) {
-                Hsp[q] = Hs[q];
-                Ecp[q] = Ecn[q];
-                Cr[q] = Cx[q];
+                for (int q = 0; q < C; ++q) {
+                    if (TE) {
+                        inD[q] = oD[q];
+                        inB[q] = oB[q];
+                        nxt[st + 1][q] = oC[q];
+                    } else {
+                        inC[q] = oC[q];
+                        nxt[st + 1][q] = oD[q];
+                        nxt2[st + 1][q] = oB[q];
+                    }
+                }
+            } else if (j >= i0 && j < i1) {
+                const int64_t o = (int64_t)j * ld;
+                store_rows<R, C>(Dout + o, r0, vlo, vhi, oD);
+                store_rows<R, C>(Bout + o, r0, vlo, vhi < nh ? vhi : nh, oB);
+                store_rows<R, C>(Cout + o, r0, vlo, vhi < nc ? vhi : nc, oC);
             }
         }
+#pragma unroll
+        for (int st = 1; st < T; ++st)
+#pragma unroll
+            for (int q = 0; q < C; ++q) {
+                dl[st][q] = nxt[st][q];
+                if (!TE)
+                    dl2[st][q] = nxt2[st][q];
+            }
     }
 }
 
@@ -531,46 +624,65 @@ __global__ __launch_bounds__(256) void k_prep2d(const Run2D *__restrict__ rdp)
     }
 }
 
-template <typename R, int C>
+template <typename R, int C, int T>
 hipError_t step_as(const Run2D &h, const Launch2D &L, int64_t n, int par, hipStream_t s)
 {
     const dim3 grid((unsigned)L.blocks), block(256);
     const bool te = h.pol == GFDTD2D_TE, cola = h.beta >= 0.0;
     const int xch = L.xch, ns = (int)L.nstrips, waves = (int)L.waves, blocks = (int)L.blocks;
     if (te && cola)
-        hipLaunchKernelGGL((k_step2d<R, C, true, true>), grid, block, 0, s, h, n, par, xch,
+        hipLaunchKernelGGL((k_step2d<R, C, true, true, T>), grid, block, 0, s, h, n, par, xch,
                            ns, waves, blocks);
     else if (te)
-        hipLaunchKernelGGL((k_step2d<R, C, true, false>), grid, block, 0, s, h, n, par, xch,
+        hipLaunchKernelGGL((k_step2d<R, C, true, false, T>), grid, block, 0, s, h, n, par, xch,
                            ns, waves, blocks);
     else if (cola)
-        hipLaunchKernelGGL((k_step2d<R, C, false, true>), grid, block, 0, s, h, n, par, xch,
+        hipLaunchKernelGGL((k_step2d<R, C, false, true, T>), grid, block, 0, s, h, n, par, xch,
                            ns, waves, blocks);
     else
-        hipLaunchKernelGGL((k_step2d<R, C, false, false>), grid, block, 0, s, h, n, par, xch,
-                           ns, waves, blocks);
+        hipLaunchKernelGGL((k_step2d<R, C, false, false, T>), grid, block, 0, s, h, n, par,
+                           xch, ns, waves, blocks);
     return hipGetLastError();
+}
+
+// Instantiated tilings: several steps a launch for the narrow lanes only
+// (FP32 2 or 4 cells, FP64 2): wider lanes exceed the register file there.
+template <typename R, int C>
+hipError_t step_ct(const Run2D &h, const Launch2D &L, int64_t n, int par, hipStream_t s)
+{
+    constexpr bool narrow = C * sizeof(R) <= 16;
+    switch (L.T) {
+    case 1: return step_as<R, C, 1>(h, L, n, par, s);
+    case 2: if constexpr (narrow) return step_as<R, C, 2>(h, L, n, par, s); else break;
+    case 4: if constexpr (narrow) return step_as<R, C, 4>(h, L, n, par, s); else break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-int64_t strip_rows(int C) { return 64 * (int64_t)C - 2 * HALO2D; }
+int64_t strip_rows(int C, int T) { return 64 * (int64_t)C - 2 * halo_rows(T); }
 
-Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch)
+Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch, int T)
 {
     Launch2D L;
+    (void)precision;
     if (C <= 0)
-        C = precision == GFDTD_F32 ? 4 : 2;
+        C = 2;
+    if (T <= 0)
+        T = 1;
     L.C = C;
-    L.nstrips = (nz + strip_rows(C) - 1) / strip_rows(C);
+    L.T = T;
+    L.nstrips = (nz + strip_rows(C, T) - 1) / strip_rows(C, T);
     if (xch <= 0) {
-        // 2..8 columns a wave, fewer when the grid gives under ~8 waves per
-        // SIMD (1024 SIMDs): on the 4096 x 4096 grid 8 columns (8704 FP32,
-        // 17920 FP64 waves) beat both shorter marches (more warm-up columns)
-        // and longer ones (fewer waves in flight)
-        const int64_t want = 8192;
-        int64_t x = nx * L.nstrips / want;
-        xch = (int)(x < 2 ? 2 : (x > 8 ? 8 : x));
+        // 8 T columns a wave (a march of T steps starts T + 1 columns early),
+        // fewer when the grid would give under 2048 waves.  Measured on the
+        // 4096 x 4096 grid: FP32 2 cells per lane at T = 4 best with 32
+        // columns, FP64 2 cells at T = 2 with 16, one step a launch with 8-16
+        const int64_t x = nx * L.nstrips / 2048;
+        const int64_t cap = 8 * (int64_t)T;
+        xch = (int)(x < 2 ? 2 : (x > cap ? cap : x));
     }
     if (xch > nx)
         xch = (int)nx;
@@ -595,15 +707,17 @@ hipError_t launch_step2d(const Run2D &h, const Launch2D &L, int64_t n, int par,
                          hipStream_t s)
 {
     if (h.precision == GFDTD_F32) {
+        if (L.C == 2)
+            return step_ct<float, 2>(h, L, n, par, s);
         if (L.C == 4)
-            return step_as<float, 4>(h, L, n, par, s);
+            return step_ct<float, 4>(h, L, n, par, s);
         if (L.C == 8)
-            return step_as<float, 8>(h, L, n, par, s);
+            return step_ct<float, 8>(h, L, n, par, s);
     } else {
         if (L.C == 2)
-            return step_as<double, 2>(h, L, n, par, s);
+            return step_ct<double, 2>(h, L, n, par, s);
         if (L.C == 4)
-            return step_as<double, 4>(h, L, n, par, s);
+            return step_ct<double, 4>(h, L, n, par, s);
     }
     return hipErrorInvalidValue;
 }

@@ -294,7 +294,10 @@ struct gfdtd2d_run {
     int64_t steps = 0;
     Layout2D L;
     Run2D host{};
-    Launch2D launch;
+    Launch2D launch;             // T steps a launch
+    Launch2D single;             // one step a launch (a pass's last steps)
+    int64_t launches = 0;
+    int final_par = 0;           // the half of each pair the pass ended in
     std::vector<double> eps, mu, prof, omegas, init[3];
     std::vector<int64_t> px, pz;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -326,14 +329,26 @@ gfdtd_status prepare2d(const gfdtd2d_problem *p, int64_t steps, const gfdtd2d_ex
                     sizeof(gfdtd2d_exec));
     int C = ex ? ex->cells_per_lane : 0;
     const int xch = ex ? ex->columns_per_wave : 0;
+    int T = ex ? ex->block_steps : 0;
     if (C != 0) {
-        const bool ok = p->precision == GFDTD_F32 ? (C == 4 || C == 8) : (C == 2 || C == 4);
+        const bool ok = p->precision == GFDTD_F32 ? (C == 2 || C == 4 || C == 8)
+                                                  : (C == 2 || C == 4);
         if (!ok)
             return fail(GFDTD_E_INVALID, "cells_per_lane %d not available for this "
-                        "precision (FP32: 4, 8; FP64: 2, 4)", C);
+                        "precision (FP32: 2, 4, 8; FP64: 2, 4)", C);
     }
     if (xch < 0 || xch > 4096)
         return fail(GFDTD_E_INVALID, "columns_per_wave %d outside 0..4096", xch);
+    if (T != 0 && T != 1 && T != 2 && T != 4)
+        return fail(GFDTD_E_INVALID, "block_steps %d not 0, 1, 2 or 4", T);
+    const int narrow = p->precision == GFDTD_F32 ? 4 : 2;     // widest multi-step lane
+    const bool ring = p->abc == GFDTD_ABC_PERIODIC;
+    if (T > 1 && ((C != 0 && C > narrow) || ring))
+        return fail(GFDTD_E_INVALID, "block_steps %d needs at most %d cells per lane "
+                    "and non-periodic ends", T, narrow);
+    if (T == 0)   // several steps a launch where the tiling allows it (measured
+                  // best: FP32 four, FP64 two, both at 2 cells per lane)
+        T = (ring || (C != 0 && C > narrow)) ? 1 : (p->precision == GFDTD_F32 ? 4 : 2);
     Layout2D L = carve2d(p, steps);
     if (!ws || ws_bytes < L.total)
         return fail(GFDTD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
@@ -364,7 +379,6 @@ gfdtd_status prepare2d(const gfdtd2d_problem *p, int64_t steps, const gfdtd2d_ex
     r->p.probe_z = r->pz.data();
     r->p.init_d = r->p.init_b = r->p.init_c = nullptr;
 
-    const bool ring = p->abc == GFDTD_ABC_PERIODIC;
     Run2D &h = r->host;
     char *base = r->ws;
     h.nx = nx;
@@ -397,7 +411,8 @@ gfdtd_status prepare2d(const gfdtd2d_problem *p, int64_t steps, const gfdtd2d_ex
         h.f[f] = base + L.field[f];
     for (int f = 0; f < 3; ++f)
         h.init[f] = init[f] ? reinterpret_cast<const double *>(base + L.init[f]) : nullptr;
-    r->launch = plan_launch2d(nx, nz, p->precision, C, xch);
+    r->launch = plan_launch2d(nx, nz, p->precision, C, xch, T);
+    r->single = plan_launch2d(nx, nz, p->precision, r->launch.C, r->launch.xch, 1);
 
     DftDesc dd{};
     dd.steps = steps;
@@ -446,9 +461,18 @@ gfdtd_status run_pass2d(gfdtd2d_run *r)
         return hip_fail(e, "2D prep launch");
     if ((e = hipEventRecord(r->ev[1], r->stream)))
         return hip_fail(e, "event");
-    for (int64_t n = 1; n <= r->steps; ++n)
-        if ((e = launch_step2d(r->host, r->launch, n, (int)((n - 1) & 1), r->stream)))
+    int par = 0;
+    int64_t launches = 0;
+    for (int64_t n = 1; n <= r->steps;) {
+        const Launch2D &L = (r->steps - n + 1 >= r->launch.T) ? r->launch : r->single;
+        if ((e = launch_step2d(r->host, L, n, par, r->stream)))
             return hip_fail(e, "2D step launch");
+        n += L.T;
+        par ^= 1;
+        ++launches;
+    }
+    r->launches = launches;
+    r->final_par = par;
     if ((e = hipEventRecord(r->ev[2], r->stream)))
         return hip_fail(e, "event");
     if (r->p.nprobe * r->p.nfreq > 0 && r->steps > 0) {
@@ -503,8 +527,8 @@ gfdtd_status collect2d(gfdtd2d_run *r, gfdtd2d_result *out)
         }
     if (want_trace && !trace.empty())
         std::memcpy(out->trace, trace.data(), trace.size() * 8);
-    // final fields: the half of each pair the last step wrote
-    const int fin = (int)(steps & 1);
+    // final fields: the half of each pair the last launch wrote
+    const int fin = r->final_par;
     const size_t w = p.precision == GFDTD_F32 ? 4 : 8;
     const int64_t nx = p.nx, nz = p.nz, ld = r->host.ld;
     const int64_t nlat[3] = {nz, r->host.nh, r->host.nc};
@@ -590,7 +614,8 @@ gfdtd_status gfdtd2d_get_stats(const gfdtd2d_run *r, gfdtd2d_stats *s)
     s->cells_per_lane = r->launch.C;
     s->columns_per_wave = r->launch.xch;
     s->waves = (int32_t)r->launch.waves;
-    s->launches = r->steps;
+    s->launches = r->launches;
+    s->block_steps = r->launch.T;
     s->cell_updates = (double)r->p.nx * (double)r->p.nz * (double)r->steps;
     s->step_ms = r->step_ms;
     s->pass_ms = r->pass_ms;

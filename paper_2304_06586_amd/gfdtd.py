@@ -138,7 +138,7 @@ class gfdtd2d_result(C.Structure):
 class gfdtd2d_exec(C.Structure):
     _fields_ = [
         ("struct_size", C.c_uint32), ("cells_per_lane", C.c_int32),
-        ("columns_per_wave", C.c_int32), ("reserved0", C.c_int32),
+        ("columns_per_wave", C.c_int32), ("block_steps", C.c_int32),
     ]
 
 
@@ -148,6 +148,7 @@ class gfdtd2d_stats(C.Structure):
         ("columns_per_wave", C.c_int32), ("waves", C.c_int32),
         ("launches", C.c_int64), ("cell_updates", C.c_double),
         ("step_ms", C.c_double), ("pass_ms", C.c_double),
+        ("block_steps", C.c_int32), ("reserved0", C.c_int32),
     ]
 
 
@@ -783,7 +784,7 @@ class Run2D:
     """gfdtd2d_prepare / run_pass / collect / get_stats / destroy."""
 
     def __init__(self, problem, steps=None, cells_per_lane=0, columns_per_wave=0,
-                 stream=None, record_trace=True, fields=True):
+                 block_steps=0, stream=None, record_trace=True, fields=True):
         import torch
         self._lib = load_library()
         self._m = _Marshalled2D(problem, steps)
@@ -800,6 +801,7 @@ class Run2D:
         e.struct_size = C.sizeof(gfdtd2d_exec)
         e.cells_per_lane = int(cells_per_lane)
         e.columns_per_wave = int(columns_per_wave)
+        e.block_steps = int(block_steps)
         self._exec = e
         h = C.c_void_p(None)
         _check(self._lib.gfdtd2d_prepare(
@@ -820,7 +822,8 @@ class Run2D:
         s = gfdtd2d_stats()
         s.struct_size = C.sizeof(gfdtd2d_stats)
         _check(self._lib.gfdtd2d_get_stats(self._h, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in gfdtd2d_stats._fields_ if k != "struct_size"}
+        return {k: getattr(s, k) for k, _ in gfdtd2d_stats._fields_
+                if k not in ("struct_size", "reserved0")}
 
     def close(self):
         if self._h:

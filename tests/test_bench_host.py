@@ -91,7 +91,7 @@ def test_2d_roofline_and_its_counters(tmp_path, monkeypatch):
                     "fetch_bytes_per_update: 14.5\nwrite_bytes_per_update: 12.0\n")
     monkeypatch.setitem(bench.COUNTERS_2D, (W.TE, W.F32), str(prof))
     st = {"launches": 100, "step_ms": 10.0, "cell_updates": 100 * 2.0e7,
-          "cells_per_lane": 4, "columns_per_wave": 8, "waves": 1000}
+          "cells_per_lane": 4, "columns_per_wave": 8, "waves": 1000, "block_steps": 1}
     r = bench.kernel_roofline_2d(st, W.TE, W.F32)
     assert r["bound"] == "hbm" and r["unit"] == "GB/s"
     assert abs(r["achieved"] - 2.0e7 * 24 / 1e-4 / 1e9) < 0.1      # 4800 GB/s
@@ -105,6 +105,13 @@ def test_2d_roofline_and_its_counters(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "KERNEL2D_SRC", str(other))
     st["columns_per_wave"] = 8
     assert bench.kernel_roofline_2d(st, W.TE, W.F32)["traffic"] is None
+    # two steps a launch: each launch still moves 6 words a cell, 3 per
+    # cell-update; the single-step equivalent doubles
+    st.update(block_steps=2, cell_updates=100 * 4.0e7)
+    r2 = bench.kernel_roofline_2d(st, W.TE, W.F32)
+    assert abs(r2["achieved"] - r["achieved"]) < 0.1 and r2["bytes_per_update"] == 12
+    assert abs(r2["single_step_hbm_equiv_GBs"] - 2 * r["achieved"]) < 0.2
+    assert r2["traffic"] is None                       # counters were taken at T = 1
 
 
 def test_serving_driver_counts_latency_and_queueing(monkeypatch):

@@ -126,25 +126,52 @@ def test_zero_steps_return_the_initial_state(P):
     assert not np.any(got["b"])
 
 
-@pytest.mark.parametrize("precision,cells", [(W.F32, (4, 8)), (W.F64, (2, 4))])
-def test_execution_options_do_not_change_results(P, precision, cells):
+@pytest.mark.parametrize("precision,narrow,wide", [(W.F32, 4, 8), (W.F64, 2, 4)])
+def test_execution_options_do_not_change_results(P, precision, narrow, wide):
+    """Cells per lane, columns per wave and steps per launch change nothing,
+    bit for bit (301 steps: the multi-step launches end with single
+    steps)."""
+    tilings = [(narrow, x, t) for t in (1, 2, 4) for x in (1, 3, 16, 64)]
+    tilings += [(wide, x, 1) for x in (1, 8)]
     for pol in (W.TE, W.TM):
-        p = W.small_case_2d(41, 1500, 300, -0.3, pol=pol, precision=precision, seed=2,
+        p = W.small_case_2d(41, 1500, 301, -0.3, pol=pol, precision=precision, seed=2,
                             m=3, structure="slab")
         ref = None
-        for C in cells:
-            for xch in (1, 3, 16, 64):
-                with P.Run2D(p, cells_per_lane=C, columns_per_wave=xch) as r:
-                    r.run()
-                    out = r.collect()
-                    st = r.stats()
-                assert st["cells_per_lane"] == C and st["columns_per_wave"] == min(xch, 41)
-                if ref is None:
-                    ref = out
-                    continue
-                for k in ("d", "b", "c", "trace"):
-                    diff = float(np.max(np.abs(out[k] - ref[k])))
-                    assert np.array_equal(out[k], ref[k]), (pol, C, xch, k, diff)
+        for C, xch, T in tilings:
+            with P.Run2D(p, cells_per_lane=C, columns_per_wave=xch, block_steps=T) as r:
+                r.run()
+                out = r.collect()
+                st = r.stats()
+            assert st["cells_per_lane"] == C and st["columns_per_wave"] == min(xch, 41)
+            assert st["block_steps"] == T and st["launches"] == 301 // T + 301 % T
+            if ref is None:
+                ref = out
+                continue
+            for k in ("d", "b", "c", "trace"):
+                diff = float(np.max(np.abs(out[k] - ref[k])))
+                assert np.array_equal(out[k], ref[k]), (pol, C, xch, T, k, diff)
+
+
+def test_multi_step_launches_near_the_grid_ends(P):
+    """Short grids where the last strips hold the ends in their halo rows
+    and the lattices end in different strips (nz = STRIDE + 1, + 2): four
+    steps a launch against one, bit for bit, and against the oracle."""
+    for precision, C in ((W.F32, 4), (W.F64, 2)):
+        stride = 64 * C - 2 * 12
+        for nz in (stride + 1, stride + 2, 2 * stride - 1):
+            for pol in (W.TE, W.TM):
+                for beta in (0.4, -0.4):
+                    p = W.small_case_2d(6, nz, 120, beta, pol=pol, precision=precision,
+                                        seed=nz, structure="random")
+                    outs = []
+                    for T in (1, 4):
+                        with P.Run2D(p, block_steps=T) as r:
+                            r.run()
+                            outs.append(r.collect())
+                    for k in ("d", "b", "c", "trace"):
+                        assert np.array_equal(outs[0][k], outs[1][k]), (precision, nz, pol, beta, k)
+                    if precision == W.F64:
+                        compare(outs[1], stepper2d.solve(p), TOL64, f"ends {nz} {pol} {beta}")
 
 
 def test_repeated_passes_are_identical(P):

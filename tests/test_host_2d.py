@@ -147,3 +147,31 @@ def test_workspace_bytes_scale_with_the_grid(P):
     fa, fb = 6 * 64 * 1024 * 4, 6 * 64 * 1024 * 8
     assert fa < a < fa + 200_000
     assert fb < b < fb + 200_000
+
+
+def test_execution_options_are_validated_before_the_device(P):
+    """gfdtd2d_prepare checks its options before touching the device: a bad
+    option is E_INVALID, a good one then fails on the missing workspace."""
+    import ctypes as C
+    from paper_2304_06586_amd import gfdtd as G
+    lib = G.load_library()
+
+    def prepare(p, cells=0, cols=0, steps_per_launch=0):
+        m = G._Marshalled2D(p)
+        e = G.gfdtd2d_exec()
+        e.struct_size = C.sizeof(G.gfdtd2d_exec)
+        e.cells_per_lane, e.columns_per_wave, e.block_steps = cells, cols, steps_per_launch
+        h = C.c_void_p(None)
+        return lib.gfdtd2d_prepare(C.byref(m.struct), m.steps, C.byref(e), None, 0, None,
+                                   C.byref(h))
+    p32 = W.small_case_2d(8, 64, 10, 0.2, precision=W.F32)
+    p64 = W.small_case_2d(8, 64, 10, 0.2, precision=W.F64)
+    ring = W.small_case_2d(8, 64, 10, 0.2, precision=W.F32, abc=W.ABC_PERIODIC)
+    assert prepare(p32, steps_per_launch=3) == 1
+    assert prepare(p32, cells=8, steps_per_launch=2) == 1     # wide lanes: one step
+    assert prepare(p64, cells=4, steps_per_launch=4) == 1
+    assert prepare(ring, steps_per_launch=2) == 1             # rings: one step
+    assert prepare(p32, cells=3) == 1
+    assert prepare(p64, cells=8) == 1
+    for ok in ((p32, 4, 0, 4), (p32, 2, 0, 2), (p64, 2, 0, 2), (ring, 0, 0, 1), (p32, 8, 16, 1)):
+        assert prepare(ok[0], ok[1], ok[2], ok[3]) == 3        # E_NOMEM: no workspace
