@@ -148,7 +148,7 @@ gfdtd_status gfdtd2d_workspace_bytes(const gfdtd2d_problem *p, int64_t steps,
  * Execution options (NULL = automatic).  cells_per_lane: z cells a lane
  * holds (FP32: 2, 4 or 8, FP64: 2 or 4; 0 = auto); columns_per_wave:
  * columns a wave steps in one launch (0 = auto); block_steps: steps a
- * launch advances the grid, 1, 2 or 4 (0 = auto); more than 1 needs the
+ * launch advances the grid, 1 to 4 (0 = auto); more than 1 needs the
  * narrow lanes (FP32 at most 4 cells, FP64 2) and ends other than
  * periodic.  A run whose
  * step count is not a multiple finishes with one-step launches.  Results

@@ -24,7 +24,7 @@
 // computed but not stored).  Blocks of 4 waves are numbered so that each
 // XCD takes a contiguous range of strips.
 //
-// Temporal blocking: a launch may advance the grid by T steps (T = 2 or 4
+// Temporal blocking: a launch may advance the grid by T steps (T = 2..4
 // off a z-ring).  The march then runs T stages, stage t one column behind
 // stage t - 1 and taking its input fields from registers, so a cell-update
 // moves 6/T words through HBM plus the warm-up columns; strips overlap by
@@ -32,12 +32,13 @@
 // rows off the grid take the fields' edge values again, as the step reads
 // them.
 //
-// Arithmetic follows the oracle's order of operations per term (division
-// by eps, mu replaced by a multiply with the reciprocal), with floating-point
-// contraction off in this file: every cell-update is the same sequence of
-// roundings wherever the cell sits in a strip or chunk, so results do not
-// depend on the launch geometry, and FP64 runs agree with the oracle to
-// rounding.
+// Arithmetic: each update is the oracle's sum of terms, with division by
+// eps, mu replaced by a multiply with the reciprocal and each term's
+// product folded into a fused multiply-add written out as one.
+// Floating-point contraction is off in this file, so every cell-update is
+// the same sequence of roundings wherever the cell sits in a strip, chunk
+// or stage: results do not depend on the launch geometry (bit for bit), and
+// FP64 runs agree with the oracle to rounding.
 
 #include <hip/hip_runtime.h>
 
@@ -88,6 +89,12 @@ __device__ __forceinline__ double lane_right(double v)
     const int hi = dpp_right((int)(u >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+
+// Fused multiply-add, written out: contraction is off in this file, so
+// every fused operation is one of these and the same in every copy of a
+// stage, whatever the tiling.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Row shifts of a lane's C consecutive rows: the value at row r-1, r-2, r+1.
 template <typename R, int C>
@@ -258,7 +265,10 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
     const int i1 = i0 + xch < nx ? i0 + xch : nx;
 
     const double Sd = rd.S, betad = rd.beta, bSd = betad * Sd;
-    const R S = (R)Sd, beta = (R)betad, bS = (R)bSd, half = (R)0.5;
+    // S, -S, -beta S and +-beta/2 (the sign of the star fields' velocity
+    // part: TE +, TM -)
+    const R S = (R)Sd, nS = (R)(-Sd), nbS = (R)(-bSd);
+    const R hb = (R)(TE ? 0.5 * betad : -0.5 * betad);
 
     // the rows a wave holds that need the source, the ends or the grid-edge
     // values (halo rows included: later stages read them)
@@ -340,8 +350,8 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
         }
 #pragma unroll
         for (int q = 0; q < C; ++q) {
-            const R bb = half * (a1[q] + a2[q]);
-            E[q] = TE ? D[q] * cE[q] + beta * bb : D[q] * cE[q] - beta * bb;
+            // D/eps +- beta (B1 + B2)/2, hb = +-beta/2
+            E[q] = fmad(hb, a1[q] + a2[q], D[q] * cE[q]);
         }
     };
     // Table 1 upwind z-difference: F - F(r-1) (v >= 0) or F(r+1) - F (v < 0)
@@ -489,16 +499,16 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
                 dz_up(k2[st], dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    oB[q] = k2[st][q] + S * (t1[q] - k3[st][q]) - bS * dd[q];
+                    oB[q] = fmad(nbS, dd[q], fmad(S, t1[q] - k3[st][q], k2[st][q]));
                 dz_up(Cj, dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    oC[q] = Cj[q] - S * (En[q] - k3[st][q]) - bS * dd[q];
+                    oC[q] = fmad(nbS, dd[q], fmad(nS, En[q] - k3[st][q], Cj[q]));
                 // (10d): H*_x = B_x/mu + beta Dbar, H*_z = B_z/mu
                 next1<R, C>(k1[st], t1);
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
-                    Hs[q] = oB[q] * chB[st][q] + beta * (half * (t1[q] + k1[st][q]));
+                    Hs[q] = fmad(hb, t1[q] + k1[st][q], oB[q] * chB[st][q]);
                     Hc[q] = oC[q] * cc[st][q];
                 }
                 // (10b): D_y^{n+1/2}
@@ -506,8 +516,8 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
                 dz_up(k1[st], dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    oD[q] = k1[st][q] + S * (Hs[q] - t2[q]) - S * (Hc[q] - k4[st][q]) -
-                            bS * dd[q];
+                    oD[q] = fmad(nbS, dd[q], fmad(nS, Hc[q] - k4[st][q],
+                                                  fmad(S, Hs[q] - t2[q], k1[st][q])));
                 finish_d(st, j, k1[st], oD);
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
@@ -534,22 +544,23 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
                 dz_up(Bj, dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    oB[q] = Bj[q] - S * (t1[q] - Es[q]) + S * (Ecn[q] - k2[st][q]) - bS * dd[q];
+                    oB[q] = fmad(nbS, dd[q], fmad(S, Ecn[q] - k2[st][q],
+                                                  fmad(nS, t1[q] - Es[q], Bj[q])));
                 // (10d): H*_y = B_y/mu - beta Dbar
                 next1<R, C>(Dj, t1);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    Hs[q] = oB[q] * chB[st][q] - beta * (half * (t1[q] + Dj[q]));
+                    Hs[q] = fmad(hb, t1[q] + Dj[q], oB[q] * chB[st][q]);
                 // (10b): D_x^{n+1/2} and D_z^{n+1/2}
                 prev1<R, C>(Hs, t2);
                 dz_up(Dj, dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    oD[q] = Dj[q] - S * (Hs[q] - t2[q]) - bS * dd[q];
+                    oD[q] = fmad(nbS, dd[q], fmad(nS, Hs[q] - t2[q], Dj[q]));
                 dz_up(k1[st], dd);
 #pragma unroll
                 for (int q = 0; q < C; ++q)
-                    oC[q] = k1[st][q] + S * (Hs[q] - k3[st][q]) - bS * dd[q];
+                    oC[q] = fmad(nbS, dd[q], fmad(S, Hs[q] - k3[st][q], k1[st][q]));
                 finish_d(st, j, Dj, oD);
 #pragma unroll
                 for (int q = 0; q < C; ++q) {
@@ -654,6 +665,7 @@ hipError_t step_ct(const Run2D &h, const Launch2D &L, int64_t n, int par, hipStr
     switch (L.T) {
     case 1: return step_as<R, C, 1>(h, L, n, par, s);
     case 2: if constexpr (narrow) return step_as<R, C, 2>(h, L, n, par, s); else break;
+    case 3: if constexpr (narrow) return step_as<R, C, 3>(h, L, n, par, s); else break;
     case 4: if constexpr (narrow) return step_as<R, C, 4>(h, L, n, par, s); else break;
     default: break;
     }
@@ -676,12 +688,14 @@ Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch, in
     L.T = T;
     L.nstrips = (nz + strip_rows(C, T) - 1) / strip_rows(C, T);
     if (xch <= 0) {
-        // 8 T columns a wave (a march of T steps starts T + 1 columns early),
+        // a march of T steps starts T + 1 columns early, so deeper blocks
+        // want longer marches: at most 8, 16, 16, 32 columns for T = 1..4,
         // fewer when the grid would give under 2048 waves.  Measured on the
-        // 4096 x 4096 grid: FP32 2 cells per lane at T = 4 best with 32
-        // columns, FP64 2 cells at T = 2 with 16, one step a launch with 8-16
+        // 4096 x 4096 grid at 2 cells per lane: FP32 T = 3 best with 16
+        // columns, FP64 T = 4 with 32, one step a launch with 8-16
+        static const int cap_of[5] = {8, 8, 16, 16, 32};
         const int64_t x = nx * L.nstrips / 2048;
-        const int64_t cap = 8 * (int64_t)T;
+        const int64_t cap = cap_of[T < 0 ? 0 : (T > 4 ? 4 : T)];
         xch = (int)(x < 2 ? 2 : (x > cap ? cap : x));
     }
     if (xch > nx)

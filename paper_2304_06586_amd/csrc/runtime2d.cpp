@@ -339,16 +339,16 @@ gfdtd_status prepare2d(const gfdtd2d_problem *p, int64_t steps, const gfdtd2d_ex
     }
     if (xch < 0 || xch > 4096)
         return fail(GFDTD_E_INVALID, "columns_per_wave %d outside 0..4096", xch);
-    if (T != 0 && T != 1 && T != 2 && T != 4)
-        return fail(GFDTD_E_INVALID, "block_steps %d not 0, 1, 2 or 4", T);
+    if (T < 0 || T > 4)
+        return fail(GFDTD_E_INVALID, "block_steps %d outside 0..4", T);
     const int narrow = p->precision == GFDTD_F32 ? 4 : 2;     // widest multi-step lane
     const bool ring = p->abc == GFDTD_ABC_PERIODIC;
     if (T > 1 && ((C != 0 && C > narrow) || ring))
         return fail(GFDTD_E_INVALID, "block_steps %d needs at most %d cells per lane "
                     "and non-periodic ends", T, narrow);
     if (T == 0)   // several steps a launch where the tiling allows it (measured
-                  // best: FP32 four, FP64 two, both at 2 cells per lane)
-        T = (ring || (C != 0 && C > narrow)) ? 1 : (p->precision == GFDTD_F32 ? 4 : 2);
+                  // best: FP32 three, FP64 four, both at 2 cells per lane)
+        T = (ring || (C != 0 && C > narrow)) ? 1 : (p->precision == GFDTD_F32 ? 3 : 4);
     Layout2D L = carve2d(p, steps);
     if (!ws || ws_bytes < L.total)
         return fail(GFDTD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);

@@ -130,9 +130,11 @@ def test_zero_steps_return_the_initial_state(P):
 def test_execution_options_do_not_change_results(P, precision, narrow, wide):
     """Cells per lane, columns per wave and steps per launch change nothing,
     bit for bit (301 steps: the multi-step launches end with single
-    steps)."""
-    tilings = [(narrow, x, t) for t in (1, 2, 4) for x in (1, 3, 16, 64)]
+    steps); FP32 also at 2 cells per lane."""
+    tilings = [(narrow, x, t) for t in (1, 2, 3, 4) for x in (1, 3, 16, 64)]
     tilings += [(wide, x, 1) for x in (1, 8)]
+    if precision == W.F32:
+        tilings += [(2, x, t) for t in (1, 3) for x in (5, 32)]
     for pol in (W.TE, W.TM):
         p = W.small_case_2d(41, 1500, 301, -0.3, pol=pol, precision=precision, seed=2,
                             m=3, structure="slab")

@@ -167,7 +167,7 @@ def test_execution_options_are_validated_before_the_device(P):
     p32 = W.small_case_2d(8, 64, 10, 0.2, precision=W.F32)
     p64 = W.small_case_2d(8, 64, 10, 0.2, precision=W.F64)
     ring = W.small_case_2d(8, 64, 10, 0.2, precision=W.F32, abc=W.ABC_PERIODIC)
-    assert prepare(p32, steps_per_launch=3) == 1
+    assert prepare(p32, steps_per_launch=5) == 1
     assert prepare(p32, cells=8, steps_per_launch=2) == 1     # wide lanes: one step
     assert prepare(p64, cells=4, steps_per_launch=4) == 1
     assert prepare(ring, steps_per_launch=2) == 1             # rings: one step
