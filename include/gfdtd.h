@@ -304,12 +304,12 @@ typedef struct gfdtd_stats {
 gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
 
 /*
- * Autotuner: for each (precision, kind) group of the batch, time
- * trial_blocks launches (0 = 4) of every valid (cells per lane in {4, 8,
- * 12, 16}, steps per launch in {8, 16, 24, 32, 48, 64}, 1 or 4 waves per
- * tile off rings) on the prepared runs
- * and keep the fastest per cell-update; results of a pass do not depend on
- * the choice.  Choices are cached in the process by precision, kind, sign
+ * Autotuner: for each (precision, kind) group of the batch, time every
+ * valid (cells per lane in {4, 8, 12, 16}, steps per launch in {8, 16, 24,
+ * 32, 48, 64}, 1 or 4 waves per tile off rings) on the prepared runs over
+ * about trial_blocks * 48 steps (trial_blocks 0 = 4; eight times that for a
+ * group under 4M cells, whose launches are short), and keep the fastest per
+ * cell-update; results of a pass do not depend on the choice.  Choices are cached in the process by precision, kind, sign
  * mix and the size scales of the group.  Writes the first group's choice to
  * *chosen (may be NULL).  Synchronous; leaves the fields to be re-zeroed by
  * the next gfdtd_batch_run.

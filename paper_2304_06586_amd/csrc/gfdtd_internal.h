@@ -66,6 +66,8 @@ struct RunDesc {
 struct TileRef {
     int32_t run;           // index into the RunDesc array of the launch
     int32_t tile;          // tile index within that run
+    int32_t probe_waves;   // bit w: wave w of the tile owns a probe
+    int32_t reserved;
 };
 
 // Per-run arguments of the set-up kernels.

@@ -249,6 +249,38 @@ __device__ __forceinline__ R pick_lane(const R (&a)[C], int idx, int l)
     return r;
 }
 
+// The same wave-uniform (s) or per-lane (v) integer, taken by the
+// compiler as produced anew where this is called (an empty asm statement,
+// no instruction).  Inside a step loop, masks derived from it are then
+// recomputed each step instead of being hoisted and held across the loop,
+// C of them per use: more than the scalar register file holds, and what
+// spills is reloaded each step.
+__device__ __forceinline__ int fresh_s(int v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+__device__ __forceinline__ int fresh_v(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// a[idx] for a wave-uniform idx in [0, C), as the multiply-add chain
+// sum_c [idx == c] a[c] with weights 1 and 0: exact for finite values (the
+// other terms add signed zeros), no branch and no lane mask.  (A select
+// chain on idx is turned into a branch tree by the compiler.)
+template <typename R, int C>
+__device__ __forceinline__ R pick_w(const R (&a)[C], int idx)
+{
+    R r = (idx == 0 ? (R)1 : (R)0) * a[0];
+#pragma unroll
+    for (int c = 1; c < C; ++c)
+        r = fmad(idx == c ? (R)1 : (R)0, a[c], r);
+    return r;
+}
+
 // ------------------------------------------------------------- the tile
 
 // Workgroup barrier of a multi-wave tile.  A wave takes part only while
@@ -262,10 +294,13 @@ __device__ __forceinline__ void tile_barrier()
         __syncthreads();
 }
 
-template <typename R, int C, int KIND, bool NEG, bool RING, bool WIN, bool MW>
+// EDGE: this wave runs the full step (an end, the source or a probe is in
+// it, as full_step_wave decides); every other wave runs the interior step,
+// compiled without any of that code.
+template <typename R, int C, int KIND, bool NEG, bool RING, bool WIN, bool MW, bool EDGE>
 __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                                           int tile, int w, int G_, int64_t block, int T,
-                                          R *__restrict__ xbuf)
+                                          bool ownsProbe, R *__restrict__ xbuf)
 {
     const int G = MW ? G_ : 1;          // one-wave tiles carry no refresh code
     // The full step's single-cell updates (source, end nodes, probe reads)
@@ -469,11 +504,45 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     (void)fill_h;
 
     // a ring has no ends
-    const bool touchL = !RING && x0 < 0;            // E node 0 (and ghosts)
-    const bool touchR = !RING && x0 + W > nz - 1;   // node nz-1 (and ghosts)
+    const bool touchL = EDGE && !RING && x0 < 0;            // E node 0 (and ghosts)
+    const bool touchR = EDGE && !RING && x0 + W > nz - 1;   // node nz-1 (and ghosts)
 
-    // Off the grid B takes the edge value (zero-gradient extension).
+    // Off the grid B takes the edge value (zero-gradient extension).  A
+    // cell on the grid reads only two ghost cells: B_{-1}, B_{-2} through
+    // the column a terms (E nodes 0 and 1), B_{nz-1}, B_{nz} through the
+    // column b terms (E node nz-1).  Every other off-grid value reaches
+    // only the end nodes, which the end condition then overwrites, and
+    // other off-grid cells.  Narrow lanes set just those two cells, on the
+    // side the active column reads; wide lanes fill every off-grid cell.
     auto ghosts = [&](R (&Bv)[C]) __attribute__((always_inline)) {
+        if constexpr (kSelects) {
+            if (!NEG && touchL) {
+                // x0 is a multiple of C: cell 0 is register 0 of lane
+                // l0 >= 1, the ghosts registers C-1, C-2 of lane l0 - 1
+                const int l0 = (int)(-x0 / C);
+                const R b0 = from_right(Bv[0]);
+                const bool at = fresh_v(lane) == l0 - 1;
+                Bv[C - 1] = at ? b0 : Bv[C - 1];
+                Bv[C - 2] = at ? b0 : Bv[C - 2];
+            }
+            if (NEG && touchR) {
+                // cell k = nz-1 (d + c == 0 below) takes its left neighbour,
+                // cell nz (d + c == 1) the one two to its left: both B_{nz-2}
+                const int d = fresh_v(lane) * C - (int)(nz - 1 - x0);
+                const R l1 = from_left(Bv[C - 1]), l2 = from_left(Bv[C - 2]);
+                R nb[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const R p1 = c >= 1 ? Bv[c >= 1 ? c - 1 : 0] : l1;
+                    const R p2 = c >= 2 ? Bv[c >= 2 ? c - 2 : 0] : (c == 1 ? l1 : l2);
+                    nb[c] = (d == -c) ? p1 : ((d == 1 - c) ? p2 : Bv[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    Bv[c] = nb[c];
+            }
+            return;
+        }
         if (touchL) {
             const int l0 = (int)(-x0 / C);
             const R b0 = readlane_r(Bv[0], l0);
@@ -483,8 +552,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
         if (touchR) {
             const int64_t r = nz - 2 - x0;
-            const R bl = kSelects ? pick_lane<R, C>(Bv, (int)(r % C), (int)(r / C))
-                                  : readlane_r(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
+            const R bl = readlane_r(pick<R, C>(Bv, (int)(r % C)), (int)(r / C));
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 Bv[c] = (kb + c >= nz - 1) ? bl : Bv[c];
@@ -500,7 +568,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     bool hasSrc = false;
     int ls = -1, cs = 0;
     unsigned smask = 0u;
-    if (rd->nsrc > 0) {
+    if (EDGE && rd->nsrc > 0) {
         if constexpr (RING) {
             int64_t i = kw;
 #pragma unroll
@@ -554,38 +622,46 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         }
     };
 
-    bool ownsProbe = false;
-    for (int q = 0; q < nprobe; ++q) {
-        const int64_t kp = rd->probes[q];
-        ownsProbe = ownsProbe || (kp >= own_lo && kp < own_hi);
-    }
+    // Whether this wave owns a probe comes with the tile reference (set on
+    // the host from the same owned ranges).  What the full step alone needs
+    // (the probe cells, the mask of owned probes) it computes itself: a
+    // value computed before the choice of loop stays live across the
+    // interior loop, which has no registers to spare.
 
     // Physical E = E* + beta Bbar at the owned probes, for time n-1/2
     // (E* = E~ / S).  Lane q of the probe table describes probe q: plc =
     // lane * C + register of its cell in this tile, prow = its trace row
     // (the value for time n-1/2 goes to prow[n-2]); bit q of pmask says this
     // tile owns it.
-    auto record = [&](int64_t n, int plc, double *prow, uint64_t pmask)
+    // E at time n-1/2 from E~ and the B average sm: E* + beta Bbar =
+    // E~ / S + beta sm / 2.
+    auto probe_value = [&](R e, R sm) __attribute__((always_inline)) {
+        return fmad((double)e, invS64, beta64 * (0.5 * (double)sm));
+    };
+    // The general probe path (Es and sums of every cell computed first):
+    // one probe after another from the table, the owning lane storing.
+    auto record = [&](int64_t n, int plc, double *prow, uint64_t pm)
                       __attribute__((always_inline)) {
-        if (n < 2)
-            return;
-        for (uint64_t m = pmask; m != 0ull; m &= m - 1ull) {
+        for (uint64_t m = pm; m != 0ull; m &= m - 1ull) {
             const int q = (int)__builtin_ctzll(m);
             const int pc = readlane_i(plc, q);
             double *row = reinterpret_cast<double *>(
                 readlane_i64(reinterpret_cast<int64_t>(prow), q));
-            if constexpr (kSelects) {
-                const R e = pick_lane<R, C>(Es, pc % C, pc / C);
-                const R sm = pick_lane<R, C>(sums, pc % C, pc / C);
-                // a wave-uniform value: every lane stores it to one address
-                glb(row)[n - 2] = (double)e * invS64 + beta64 * (0.5 * (double)sm);
-            } else {
-                const R e = pick<R, C>(Es, pc % C);
-                const R sm = pick<R, C>(sums, pc % C);
-                if (lane == pc / C)
-                    glb(row)[n - 2] = (double)e * invS64 + beta64 * (0.5 * (double)sm);
-            }
+            const R e = pick<R, C>(Es, pc % C);
+            const R sm = pick<R, C>(sums, pc % C);
+            if (lane == pc / C)
+                glb(row)[n - 2] = probe_value(e, sm);
         }
+    };
+    // One probe at register reg of lane pl (both wave-uniform), from Es and
+    // sums already formed: the two values picked in the vector unit, read
+    // from lane pl, and the wave-uniform result stored by every lane to one
+    // address (no branch, no change of the execution mask).
+    auto record_one = [&](int64_t n, int pl, int reg, double *row) __attribute__((always_inline)) {
+        const int rg = fresh_s(reg);
+        const R e = readlane_r(pick_w<R, C>(Es, rg), pl);
+        const R sm = readlane_r(pick_w<R, C>(sums, rg), pl);
+        glb(row)[n - 2] = probe_value(e, sm);
     };
 
     // Shifts of the coefficient windows.  Over one step the profile moves
@@ -603,15 +679,45 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             shift_window<R, C, NEG>(gh);
     };
 
-    // One time step n with fixed coefficient windows, from (Di, Bi) to
-    // (Dn, Bn).  The full step also takes the step's source sample gsrc and
-    // end coefficients cL, cR, and the probe table (plc, prow, pmask as in
-    // record).
-    auto one_step = [&](auto edge_tag, int64_t n, R gsrc, R cL, R cR, int plc,
-                        double *prow, uint64_t pmask,
+    // What the full step needs besides the fields, per 64-step chunk (see
+    // steps_loop).
+    struct EdgeChunk {
+        R src, cL, cR;          // lane j: step j's source sample, end coefficients
+        int nsrc_q;             // steps q < nsrc_q of the chunk add the source
+        int plc;                // lane q: probe q's cell in the wave (lane * C + reg)
+        double *prow;           // lane q: probe q's trace row
+        uint64_t pmask;         // bit q: this tile owns probe q
+        uint64_t prest;         // owned probes left to the general path
+        int np;                 // owned probes held as wave-uniform values (0..2)
+        int pl0, pr0, pl1, pr1; // their lane and register
+        double *row0, *row1;    // their trace rows
+    };
+
+    // One time step n (step q of its chunk) with fixed coefficient windows,
+    // from (Di, Bi) to (Dn, Bn).  The full step also adds the source,
+    // imposes the end conditions and records the probes from ec.
+    auto one_step = [&](auto edge_tag, int64_t n, int q, const EdgeChunk &ec,
                         const R (&Di)[C], const R (&Bi)[C], R (&Dn)[C], R (&Bn)[C])
                         __attribute__((always_inline)) {
         constexpr bool kEdge = decltype(edge_tag)::value;
+        // E at time n-1/2 of the owned probes (none at step 1, the run's
+        // first E time being 3/2)
+        auto probes_now = [&]() __attribute__((always_inline)) {
+            if constexpr (kSelects) {
+                if constexpr (!kMatter)
+                    compute_es(Di, Bi);
+                if (ec.np >= 1)
+                    record_one(n, ec.pl0, ec.pr0, ec.row0);
+                if (ec.np >= 2)
+                    record_one(n, ec.pl1, ec.pr1, ec.row1);
+                if (ec.prest != 0ull)
+                    record(n, ec.plc, ec.prow, ec.prest);
+            } else {
+                if constexpr (!kMatter)
+                    compute_es(Di, Bi);
+                record(n, ec.plc, ec.prow, ec.pmask);
+            }
+        };
 
         // (10a) Faraday with the Table 1 dB/dz, in telescoped form:
         //   P_k = E~_k + bS B_up(k),  B' = B + (P_k - P_{k+1}),
@@ -622,10 +728,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // column b; E~ itself is formed only where a probe needs it.
         R P[C];
         if constexpr (!kMatter) {
-            if (kEdge && pmask != 0ull) {
-                compute_es(Di, Bi);
-                record(n, plc, prow, pmask);
-            }
+            if (kEdge && ec.pmask != 0ull && n != 1)
+                probes_now();
             if constexpr (!NEG) {
                 const R Bm1 = from_left(Bi[C - 1]);
                 const R Bm2 = from_left(Bi[C - 2]);
@@ -645,8 +749,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         } else {
             compute_es(Di, Bi);
-            if (kEdge && pmask != 0ull)
-                record(n, plc, prow, pmask);
+            if (kEdge && ec.pmask != 0ull && n != 1)
+                probes_now();
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 R bsel;
@@ -691,8 +795,8 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             Dn[c] = Di[c] + (xp - X[c]);
         }
         // soft source
-        if (kEdge && hasSrc && n <= rd->nsrc) {
-            const R g = gsrc;
+        if (kEdge && hasSrc && q < ec.nsrc_q) {
+            const R g = readlane_r(ec.src, q);
             if constexpr (RING) {
                 if (smask) {
 #pragma unroll
@@ -700,11 +804,12 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                         if ((smask >> c) & 1u)
                             Dn[c] += g;
                 }
-            } else if (kSelects) {
-                const bool atS = lane == ls;
+            } else if constexpr (kSelects) {
+                // the source cell is where d + c == 0
+                const int d = fresh_v(lane) * C - (int)(ks - x0);
 #pragma unroll
                 for (int c = 0; c < C; ++c)
-                    Dn[c] = (atS && c == cs) ? Dn[c] + g : Dn[c];
+                    Dn[c] = (d == -c) ? Dn[c] + g : Dn[c];
             } else if (lane == ls) {
 #pragma unroll
                 for (int c = 0; c < C; ++c)
@@ -715,33 +820,41 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // end nodes, at time n+1/2
         if (kEdge && touchL) {
             const int l0 = (int)(-x0 / C);
-            const R v = (abc == GFDTD_ABC_MUR1) ? Di[1] + cL * (Dn[1] - Di[0]) : (R)0;
+            const R cL = readlane_r(ec.cL, q);
+            const R v = (abc == GFDTD_ABC_MUR1) ? fmad(cL, Dn[1] - Di[0], Di[1]) : (R)0;
             Dn[0] = (lane == l0) ? v : Dn[0];
         }
         if (kEdge && touchR) {
             const int64_t r = nz - 1 - x0;
             const int lr = (int)(r / C);
             const int cr = (int)(r % C);
+            const R cR = readlane_r(ec.cR, q);
             const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
             const bool atR = lane == lr;
             if constexpr (kSelects) {
-                // only register cr of lane lr changes, so a later register's
-                // left neighbour is never one rewritten here
+                // the end node (d + c == 0) from its left neighbour's old and
+                // new values, formed in every cell and kept in that one
+                const int d = fresh_v(lane) * C - (int)r;
+                const bool mur = abc == GFDTD_ABC_MUR1;
+                R nd[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const R po = (c >= 1) ? Di[c >= 1 ? c - 1 : 0] : dlo;
-                    const R pn = (c >= 1) ? Dn[c >= 1 ? c - 1 : 0] : dln;
-                    const R v = (abc == GFDTD_ABC_MUR1) ? po + cR * (pn - Di[c]) : (R)0;
-                    Dn[c] = (atR && c == cr) ? v : Dn[c];
+                    const R po = c >= 1 ? Di[c >= 1 ? c - 1 : 0] : dlo;
+                    const R pn = c >= 1 ? Dn[c >= 1 ? c - 1 : 0] : dln;
+                    const R v = mur ? fmad(cR, pn - Di[c], po) : (R)0;
+                    nd[c] = (d == -c) ? v : Dn[c];
                 }
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    Dn[c] = nd[c];
             } else if (atR) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     if (c == cr) {
                         const R po = (c >= 1) ? Di[c >= 1 ? c - 1 : 0] : dlo;
                         const R pn = (c >= 1) ? Dn[c >= 1 ? c - 1 : 0] : dln;
-                        Dn[c] = (abc == GFDTD_ABC_MUR1) ? po + cR * (pn - Di[c]) : (R)0;
+                        Dn[c] = (abc == GFDTD_ABC_MUR1) ? fmad(cR, pn - Di[c], po) : (R)0;
                     }
                 }
             }
@@ -822,21 +935,45 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         int mEc = mE;                       // E shift at the current n - 1/2
         int mHc = mH;                       // H shift at the current n
         int nextx = G > 1 ? xk : nsub;      // step count of the next refresh
-        // Full step only: lane q holds the cell of probe q (bit q of pmask:
-        // this tile owns it), and per 64-step chunk lane j holds step j's
-        // source sample and end coefficients (FP64), so the steps read no
-        // memory.  Kept inside this loop: declared for the whole tile they
-        // raise the register allocation of the interior loop too.
-        int plc = 0;
-        double *prow = nullptr;
-        uint64_t pmask = 0ull;
-        double srcv = 0.0, cLv = 0.0, cRv = 0.0;
+        // Full step only: the probe table (lane q: probe q), the first two
+        // owned probes as wave-uniform values, and per 64-step chunk lane j
+        // holds step j's source sample and end coefficients, so the steps
+        // read no memory.  Kept inside this loop: declared for the whole
+        // tile they raise the register allocation of the interior loop too.
+        EdgeChunk ec{};
         if constexpr (kEdge) {
+            // a compiler barrier, so this load is not merged with the one
+            // above (and the cells kept live across the interior loop)
+            asm volatile("" ::: "memory");
             const int64_t kpl = lane < nprobe ? glb(rd->probes)[lane] : (int64_t)-1;
             const bool own = lane < nprobe && kpl >= own_lo && kpl < own_hi;
-            pmask = __ballot(own);
-            plc = own ? (int)(kpl - x0) : 0;
-            prow = rd->trace + (lane < nprobe ? (int64_t)lane * steps : 0);
+            ec.pmask = __ballot(own);
+            ec.plc = own ? (int)(kpl - x0) : 0;
+            ec.prow = rd->trace + (lane < nprobe ? (int64_t)lane * steps : 0);
+            uint64_t m = ec.pmask;
+            if constexpr (kSelects) {
+                if (m != 0ull) {
+                    const int q = (int)__builtin_ctzll(m);
+                    const int pc = readlane_i(ec.plc, q);
+                    ec.pl0 = pc / C;
+                    ec.pr0 = pc % C;
+                    ec.row0 = reinterpret_cast<double *>(
+                        readlane_i64(reinterpret_cast<int64_t>(ec.prow), q));
+                    ec.np = 1;
+                    m &= m - 1ull;
+                }
+                if (m != 0ull) {
+                    const int q = (int)__builtin_ctzll(m);
+                    const int pc = readlane_i(ec.plc, q);
+                    ec.pl1 = pc / C;
+                    ec.pr1 = pc % C;
+                    ec.row1 = reinterpret_cast<double *>(
+                        readlane_i64(reinterpret_cast<int64_t>(ec.prow), q));
+                    ec.np = 2;
+                    m &= m - 1ull;
+                }
+            }
+            ec.prest = m;
         }
         for (int s0 = 0; s0 < nsub; s0 += kWave) {
             const int len = nsub - s0 < kWave ? nsub - s0 : kWave;
@@ -854,7 +991,9 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 // under the end nodes (the background one while a time
                 // window has the profile off)
                 const int64_t nl = n0 + sl;
-                srcv = (hasSrc && sl < nsub && nl <= rd->nsrc) ? glb(rd->src)[nl - 1] : 0.0;
+                double srcv = 0.0, cLv = 0.0, cRv = 0.0;
+                if (hasSrc && sl < nsub && nl <= rd->nsrc)
+                    srcv = glb(rd->src)[nl - 1];
                 if ((touchL || touchR) && abc == GFDTD_ABC_MUR1 && sl < nsub) {
                     const int mEl = profile_shift32(bS64, tn + 0.5);
                     const bool onl = !windowed || active(tn + 0.5);
@@ -863,6 +1002,12 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                     if (touchR)
                         cRv = onl ? glb(rd->murR)[clampi(nz - 1 - mEl, 0, nz - 1)] : rd->murB;
                 }
+                ec.src = (R)srcv;
+                ec.cL = (R)cLv;
+                ec.cR = (R)cRv;
+                // steps n0 + s0 + q <= nsrc take the source
+                const int64_t ns = rd->nsrc - (n0 + s0) + 1;
+                ec.nsrc_q = ns < 0 ? 0 : (ns > kWave ? kWave : (int)ns);
             }
             // finite-duration modulation: bit j of hsw / esw = the H / E
             // window switches (on or off) before / after step j; hact /
@@ -904,15 +1049,11 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 // (D, B) and (D2, B2), so no copies between steps
                 int q = j;
                 for (; q + 1 <= stop; q += 2) {
-                    one_step(edge_tag, n0 + s0 + q, (R)readlane_d(srcv, q), (R)readlane_d(cLv, q),
-                             (R)readlane_d(cRv, q), plc, prow, pmask, D, B, D2, B2);
-                    one_step(edge_tag, n0 + s0 + q + 1, (R)readlane_d(srcv, q + 1),
-                             (R)readlane_d(cLv, q + 1), (R)readlane_d(cRv, q + 1), plc, prow,
-                             pmask, D2, B2, D, B);
+                    one_step(edge_tag, n0 + s0 + q, q, ec, D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q + 1, q + 1, ec, D2, B2, D, B);
                 }
                 if (q <= stop) {
-                    one_step(edge_tag, n0 + s0 + q, (R)readlane_d(srcv, q), (R)readlane_d(cLv, q),
-                             (R)readlane_d(cRv, q), plc, prow, pmask, D, B, D2, B2);
+                    one_step(edge_tag, n0 + s0 + q, q, ec, D, B, D2, B2);
 #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         D[c] = D2[c];
@@ -941,15 +1082,13 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             }
         }
 
-        if (kEdge && last && pmask != 0ull) {   // the run ends in this block: E at N+1/2
+        if (kEdge && last && ec.pmask != 0ull) {   // the run ends in this block: E at N+1/2
             compute_es(D, B);
-            record(steps + 1, plc, prow, pmask);
+            record(steps + 1, ec.plc, ec.prow, ec.pmask);
         }
     };
-    if (touchL || touchR || hasSrc || ownsProbe)
-        steps_loop(std::true_type{});
-    else
-        steps_loop(std::false_type{});
+    (void)ownsProbe;
+    steps_loop(std::integral_constant<bool, EDGE>{});
 
     if (lane >= own_l && lane < own_r) {
         store_cells<R, C>(Ddst + kb, D);
@@ -976,6 +1115,34 @@ constexpr int occupancy_target()
     }
 }
 
+// Whether wave w of a tile runs the full step: it holds an end node (or an
+// off-grid cell), the source cell (on a ring, any copy of it), or a probe
+// it owns (owns_probe, from the tile reference).  The tile origin x0 is the
+// one tile_body computes.
+template <int C, bool RING, bool MW>
+__device__ __forceinline__ bool full_step_wave(const RunDesc *__restrict__ rd, int tile,
+                                               int w, int G_, bool owns_probe)
+{
+    if (owns_probe)
+        return true;
+    const int G = MW ? G_ : 1;
+    const int ov = G > 1 ? rd->xl + rd->xr : 0;
+    const int64_t W = (int64_t)kWave * C;
+    const int64_t nz = rd->nz;
+    const int64_t x0 = (int64_t)tile * rd->own_cells - (int64_t)rd->hl * C +
+                       (int64_t)w * (kWave - ov) * C;
+    if (!RING && (x0 < 0 || x0 + W > nz - 1))
+        return true;
+    if (rd->nsrc > 0) {
+        const int64_t ks = rd->src_cell;
+        if constexpr (RING)
+            return wrapi(ks - x0, nz) < W;       // some cell x0 + j, j < W, is ks mod nz
+        else
+            return ks >= x0 && ks < x0 + W;
+    }
+    return false;
+}
+
 // MW = false: kWavesPerGroup independent one-wave tiles per workgroup (one).
 // MW = true: one tile of G waves per workgroup (blockDim = 64 G).
 template <typename R, int C, int KIND, bool RING, bool WIN, bool MW>
@@ -998,10 +1165,26 @@ __attribute__((amdgpu_waves_per_eu(occupancy_target<R, C, KIND, MW>()))) void k_
     // so the plain kernel carries none of the window code.
     if ((KIND != GFDTD_MATTER && rd->windowed != 0) != WIN)
         return;
-    if (rd->neg)
-        tile_body<R, C, KIND, true, RING, WIN, MW>(rd, ref.tile, w, G, block, T, xbuf);
-    else
-        tile_body<R, C, KIND, false, RING, WIN, MW>(rd, ref.tile, w, G, block, T, xbuf);
+    // The choice of step loop is made here, before any work of the tile:
+    // a value the full step alone needs, computed before a branch between
+    // the two loops, would be held across the interior one too.
+    const bool owns_probe = ((ref.probe_waves >> w) & 1) != 0;
+    const bool edge = full_step_wave<C, RING, MW>(rd, ref.tile, w, G, owns_probe);
+    if (rd->neg) {
+        if (edge)
+            tile_body<R, C, KIND, true, RING, WIN, MW, true>(rd, ref.tile, w, G, block, T,
+                                                             owns_probe, xbuf);
+        else
+            tile_body<R, C, KIND, true, RING, WIN, MW, false>(rd, ref.tile, w, G, block, T,
+                                                              owns_probe, xbuf);
+    } else {
+        if (edge)
+            tile_body<R, C, KIND, false, RING, WIN, MW, true>(rd, ref.tile, w, G, block, T,
+                                                              owns_probe, xbuf);
+        else
+            tile_body<R, C, KIND, false, RING, WIN, MW, false>(rd, ref.tile, w, G, block, T,
+                                                               owns_probe, xbuf);
+    }
 }
 
 template <typename R, int KIND, bool RING, bool WIN, bool MW>

@@ -633,7 +633,7 @@ gfdtd_status Batch::build_tiles(Group &G)
         DftDesc dd;
         fill_desc(r, G, g, 0, G.host_rd[m], pd, dd);
         for (int64_t t = 0; t < nt; ++t)
-            G.host_tiles.push_back(TileRef{m, (int32_t)t});
+            G.host_tiles.push_back(make_tile_ref(r, G.host_rd[m], m, G.C, G.Gw, t));
         G.tiles_prefix[m + 1] = G.tiles_prefix[m] + nt;
         G.blocks_of[m] = (r.steps + G.T - 1) / G.T;
     }
@@ -739,7 +739,14 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                 G.Gw = Gw;
                 if ((st = build_tiles(G)) != GFDTD_OK)
                     return st;
-                const int64_t nb = std::min<int64_t>(trial + 1, G.nblocks);
+                // every candidate is timed over about the same number of
+                // steps (trial blocks of 48 steps), and a small group (a lone
+                // run: launch-bound, short launches) over at least 1536, so
+                // deeper blocks are not favoured by covering more steps or
+                // by fewer, noisier launches; block 0 is not timed
+                const int64_t span = (int64_t)trial * 48 * (cells < 4.0e6 ? 8 : 1);
+                const int64_t nb = std::min<int64_t>(
+                    std::max<int64_t>(2, (span + T - 1) / T) + 1, G.nblocks);
                 if (nb < 1)
                     continue;
                 double upd = 0.0;
@@ -826,6 +833,25 @@ void Batch::fill_desc(RunHost &r, const Group &G, const TileGeom &g, int64_t sta
                       RunDesc &rd, PrepDesc &pd, DftDesc &dd)
 {
     fill_run_desc(ws, r, G.precision, g, start_block, rd, pd, dd);
+}
+
+TileRef make_tile_ref(const RunHost &r, const RunDesc &rd, int m, int C, int G, int64_t t)
+{
+    TileRef ref{m, (int32_t)t, 0, 0};
+    // wave w's owned cells [lo, hi): k_tiles' x0, own_l and own_r
+    const int ov = G > 1 ? rd.xl + rd.xr : 0;
+    for (int w = 0; w < G; ++w) {
+        const int64_t x0 = t * rd.own_cells - (int64_t)rd.hl * C + (int64_t)w * (kWave - ov) * C;
+        const int own_l = w == 0 ? rd.hl : rd.xl;
+        const int own_r = w == G - 1 ? kWave - rd.hr : kWave - rd.xr;
+        const int64_t lo = x0 + (int64_t)own_l * C, hi = x0 + (int64_t)own_r * C;
+        for (int64_t kp : r.probes)
+            if (kp >= lo && kp < hi) {
+                ref.probe_waves |= 1 << w;
+                break;
+            }
+    }
+    return ref;
 }
 
 void fill_run_desc(char *base, const RunHost &r, int precision, const TileGeom &g,

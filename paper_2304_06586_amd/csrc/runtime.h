@@ -79,6 +79,11 @@ hipError_t upload_run_inputs(char *base, const RunHost &r, hipStream_t stream);
 void fill_run_desc(char *base, const RunHost &r, int precision, const TileGeom &g,
                    int64_t start_block, RunDesc &rd, PrepDesc &pd, DftDesc &dd);
 
+// The tile reference of tile t of run m: bit w of probe_waves is set when
+// wave w of the tile (G waves of C cells per lane) owns one of the run's
+// probes, by the owned ranges the stepping kernel uses.
+TileRef make_tile_ref(const RunHost &r, const RunDesc &rd, int m, int C, int G, int64_t t);
+
 // The state a run of zero steps returns: its initial fields (or zeros),
 // rounded to the run precision; either pointer may be null.
 void initial_fields(const RunHost &r, double *d, double *b);

@@ -565,7 +565,7 @@ struct Server {
             const int m = (int)rd.size();
             rd.push_back(d);
             for (int64_t t = 0; t < rq->ntiles; ++t)
-                tl.push_back(TileRef{m, (int32_t)t});
+                tl.push_back(make_tile_ref(rq->r, d, m, Cgrp[g], 1, t));
         }
         ntiles[g] = (int)tl.size();
         gdirty[g] = false;
