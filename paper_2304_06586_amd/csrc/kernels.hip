@@ -503,6 +503,28 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     (void)fill_e;
     (void)fill_h;
 
+    // Full step: its reads (the probe table; the first chunk's source
+    // samples and end coefficients, lane j for step j) are issued here,
+    // with the field and coefficient loads, so their latencies overlap.
+    int64_t kpl0 = -1;
+    double src0 = 0.0, cL0 = 0.0, cR0 = 0.0;
+    if constexpr (EDGE) {
+        if (lane < nprobe)
+            kpl0 = glb(rd->probes)[lane];
+        const int64_t nl = n0 + lane;
+        if (lane < nsub && nl <= rd->nsrc)
+            src0 = glb(rd->src)[nl - 1];
+        if (!RING && abc == GFDTD_ABC_MUR1 && lane < nsub) {
+            const double te = (double)nl + 0.5;
+            const int mEl = profile_shift32(bS64, te);
+            const bool onl = !windowed || active(te);
+            if (x0 < 0)
+                cL0 = onl ? glb(rd->murL)[clampi(-mEl, 0, nz - 1)] : rd->murB;
+            if (x0 + W > nz - 1)
+                cR0 = onl ? glb(rd->murR)[clampi(nz - 1 - mEl, 0, nz - 1)] : rd->murB;
+        }
+    }
+
     // a ring has no ends
     const bool touchL = EDGE && !RING && x0 < 0;            // E node 0 (and ghosts)
     const bool touchR = EDGE && !RING && x0 + W > nz - 1;   // node nz-1 (and ghosts)
@@ -514,33 +536,44 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
     // only the end nodes, which the end condition then overwrites, and
     // other off-grid cells.  Narrow lanes set just those two cells, on the
     // side the active column reads; wide lanes fill every off-grid cell.
+    // Narrow lanes, from ln = this lane, l0 = the lane whose register 0 is
+    // node 0 and dR = ln * C - (nz - 1 - x0) (node nz-1 is where dR + c ==
+    // 0); an end the wave does not hold has l0 or dR that no cell matches
+    // (end_index below).
+    auto ghosts_n = [&](R (&Bv)[C], int ln, int l0, int dR) __attribute__((always_inline)) {
+        if constexpr (!NEG) {
+            // x0 is a multiple of C: the ghosts are registers C-1, C-2 of
+            // lane l0 - 1
+            const R b0 = from_right(Bv[0]);
+            const bool at = ln == l0 - 1;
+            Bv[C - 1] = at ? b0 : Bv[C - 1];
+            Bv[C - 2] = at ? b0 : Bv[C - 2];
+        } else {
+            // cell nz-1 (dR + c == 0) takes its left neighbour, cell nz
+            // (dR + c == 1) the one two to its left: both B_{nz-2}
+            const R l1 = from_left(Bv[C - 1]), l2 = from_left(Bv[C - 2]);
+            R nb[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const R p1 = c >= 1 ? Bv[c >= 1 ? c - 1 : 0] : l1;
+                const R p2 = c >= 2 ? Bv[c >= 2 ? c - 2 : 0] : (c == 1 ? l1 : l2);
+                nb[c] = (dR == -c) ? p1 : ((dR == 1 - c) ? p2 : Bv[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                Bv[c] = nb[c];
+        }
+    };
+    constexpr int kNoCell = -(1 << 30);
+    auto end_index = [&](int ln, int &l0, int &dR) __attribute__((always_inline)) {
+        l0 = touchL ? (int)(-x0 / C) : kNoCell;
+        dR = touchR ? ln * C - (int)(nz - 1 - x0) : kNoCell;
+    };
     auto ghosts = [&](R (&Bv)[C]) __attribute__((always_inline)) {
         if constexpr (kSelects) {
-            if (!NEG && touchL) {
-                // x0 is a multiple of C: cell 0 is register 0 of lane
-                // l0 >= 1, the ghosts registers C-1, C-2 of lane l0 - 1
-                const int l0 = (int)(-x0 / C);
-                const R b0 = from_right(Bv[0]);
-                const bool at = fresh_v(lane) == l0 - 1;
-                Bv[C - 1] = at ? b0 : Bv[C - 1];
-                Bv[C - 2] = at ? b0 : Bv[C - 2];
-            }
-            if (NEG && touchR) {
-                // cell k = nz-1 (d + c == 0 below) takes its left neighbour,
-                // cell nz (d + c == 1) the one two to its left: both B_{nz-2}
-                const int d = fresh_v(lane) * C - (int)(nz - 1 - x0);
-                const R l1 = from_left(Bv[C - 1]), l2 = from_left(Bv[C - 2]);
-                R nb[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const R p1 = c >= 1 ? Bv[c >= 1 ? c - 1 : 0] : l1;
-                    const R p2 = c >= 2 ? Bv[c >= 2 ? c - 2 : 0] : (c == 1 ? l1 : l2);
-                    nb[c] = (d == -c) ? p1 : ((d == 1 - c) ? p2 : Bv[c]);
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    Bv[c] = nb[c];
-            }
+            int l0, dR;
+            end_index(lane, l0, dR);
+            ghosts_n(Bv, lane, l0, dR);
             return;
         }
         if (touchL) {
@@ -704,14 +737,16 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // first E time being 3/2)
         auto probes_now = [&]() __attribute__((always_inline)) {
             if constexpr (kSelects) {
+                // np >= 1 here (narrow lanes take the first two owned
+                // probes as wave-uniform values)
                 if constexpr (!kMatter)
                     compute_es(Di, Bi);
-                if (ec.np >= 1)
-                    record_one(n, ec.pl0, ec.pr0, ec.row0);
-                if (ec.np >= 2)
+                record_one(n, ec.pl0, ec.pr0, ec.row0);
+                if (ec.np >= 2) {
                     record_one(n, ec.pl1, ec.pr1, ec.row1);
-                if (ec.prest != 0ull)
-                    record(n, ec.plc, ec.prow, ec.prest);
+                    if (ec.prest != 0ull)
+                        record(n, ec.plc, ec.prow, ec.prest);
+                }
             } else {
                 if constexpr (!kMatter)
                     compute_es(Di, Bi);
@@ -817,7 +852,37 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                         Dn[c] += g;
             }
         }
-        // end nodes, at time n+1/2
+        // end nodes, at time n+1/2, and the ghost cells; narrow lanes do
+        // both ends in one block without branches
+        if constexpr (kSelects && !RING) {
+            if (kEdge && (touchL || touchR)) {
+                const bool mur = abc == GFDTD_ABC_MUR1;
+                const int ln = fresh_v(lane);
+                int l0, dR;
+                end_index(ln, l0, dR);
+                const R cL = readlane_r(ec.cL, q);
+                const R vL = mur ? fmad(cL, Dn[1] - Di[0], Di[1]) : (R)0;
+                Dn[0] = (ln == l0) ? vL : Dn[0];
+                // node nz-1 from its left neighbour's old and new values,
+                // formed in every cell and kept in that one
+                const R cR = readlane_r(ec.cR, q);
+                const R dlo = from_left(Di[C - 1]);
+                const R dln = from_left(Dn[C - 1]);
+                R nd[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const R po = c >= 1 ? Di[c >= 1 ? c - 1 : 0] : dlo;
+                    const R pn = c >= 1 ? Dn[c >= 1 ? c - 1 : 0] : dln;
+                    const R v = mur ? fmad(cR, pn - Di[c], po) : (R)0;
+                    nd[c] = (dR == -c) ? v : Dn[c];
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    Dn[c] = nd[c];
+                ghosts_n(Bn, ln, l0, dR);
+            }
+            return;
+        }
         if (kEdge && touchL) {
             const int l0 = (int)(-x0 / C);
             const R cL = readlane_r(ec.cL, q);
@@ -832,23 +897,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             const R dlo = from_left(Di[C - 1]);
             const R dln = from_left(Dn[C - 1]);
             const bool atR = lane == lr;
-            if constexpr (kSelects) {
-                // the end node (d + c == 0) from its left neighbour's old and
-                // new values, formed in every cell and kept in that one
-                const int d = fresh_v(lane) * C - (int)r;
-                const bool mur = abc == GFDTD_ABC_MUR1;
-                R nd[C];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    const R po = c >= 1 ? Di[c >= 1 ? c - 1 : 0] : dlo;
-                    const R pn = c >= 1 ? Dn[c >= 1 ? c - 1 : 0] : dln;
-                    const R v = mur ? fmad(cR, pn - Di[c], po) : (R)0;
-                    nd[c] = (d == -c) ? v : Dn[c];
-                }
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-                    Dn[c] = nd[c];
-            } else if (atR) {
+            if (atR) {
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     if (c == cr) {
@@ -942,10 +991,7 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
         // tile they raise the register allocation of the interior loop too.
         EdgeChunk ec{};
         if constexpr (kEdge) {
-            // a compiler barrier, so this load is not merged with the one
-            // above (and the cells kept live across the interior loop)
-            asm volatile("" ::: "memory");
-            const int64_t kpl = lane < nprobe ? glb(rd->probes)[lane] : (int64_t)-1;
+            const int64_t kpl = kpl0;
             const bool own = lane < nprobe && kpl >= own_lo && kpl < own_hi;
             ec.pmask = __ballot(own);
             ec.plc = own ? (int)(kpl - x0) : 0;
@@ -991,10 +1037,12 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 // under the end nodes (the background one while a time
                 // window has the profile off)
                 const int64_t nl = n0 + sl;
-                double srcv = 0.0, cLv = 0.0, cRv = 0.0;
-                if (hasSrc && sl < nsub && nl <= rd->nsrc)
+                // chunk 0's were read at the start of the tile
+                double srcv = s0 == 0 ? src0 : 0.0;
+                double cLv = s0 == 0 ? cL0 : 0.0, cRv = s0 == 0 ? cR0 : 0.0;
+                if (s0 > 0 && hasSrc && sl < nsub && nl <= rd->nsrc)
                     srcv = glb(rd->src)[nl - 1];
-                if ((touchL || touchR) && abc == GFDTD_ABC_MUR1 && sl < nsub) {
+                if (s0 > 0 && (touchL || touchR) && abc == GFDTD_ABC_MUR1 && sl < nsub) {
                     const int mEl = profile_shift32(bS64, tn + 0.5);
                     const bool onl = !windowed || active(tn + 0.5);
                     if (touchL)
