@@ -219,6 +219,28 @@ def test_probes_and_source_at_the_edges(P):
     compare(run(P, q), oracle.solve(q), TOL64, "edges src=nz-2")
 
 
+@pytest.mark.parametrize("kind", [W.MODULATION, W.MATTER])
+@pytest.mark.parametrize("beta", [0.3, -0.3])
+@pytest.mark.parametrize("precision", [W.F64, W.F32])
+def test_many_probes_in_the_end_waves(P, kind, beta, precision):
+    """Four probes in each end wave, on and next to the end nodes, with
+    the source next to an end: narrow lanes (4 and 8 cells per lane) keep
+    two probes as wave-uniform values and record the others by the general
+    path; the same bits as 12 cells per lane, and the oracle."""
+    nz = 1500
+    p = W.small_case(nz, 600, beta, kind=kind, structure="random", seed=11,
+                     precision=precision)
+    p = p.replace(src_cell=2 if beta > 0 else nz - 3,
+                  probes=np.array([0, 1, 2, 5, nz // 2, nz - 6, nz - 3, nz - 2, nz - 1]))
+    ref = run(P, p, cells_per_lane=12, block_steps=16, tile_waves=1, use_graph=0)
+    for C, T in ((4, 24), (8, 16), (4, 1)):
+        got = run(P, p, cells_per_lane=C, block_steps=T, tile_waves=1, use_graph=0)
+        for k in ("trace", "dft", "d", "b"):
+            assert np.array_equal(got[k], ref[k]), (C, T, k)
+    if precision == W.F64:
+        compare(ref, oracle.solve(p), TOL64, f"many probes k={kind} b={beta}")
+
+
 # ---------------------------------------------------------------------------
 # Benchmark sizes, in the launch configuration the benchmark uses
 
