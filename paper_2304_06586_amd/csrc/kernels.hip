@@ -234,21 +234,6 @@ __device__ __forceinline__ R pick(const R (&a)[C], int idx)
         return idx == I ? a[I] : pick<R, C, I - 1>(a, idx);
 }
 
-// Register idx of lane l of a lane-distributed array, for a wave-uniform
-// idx and l: every register of lane l read into a scalar, then scalar
-// selects (no branches, and the array stays in registers).
-template <typename R, int C>
-__device__ __forceinline__ R pick_lane(const R (&a)[C], int idx, int l)
-{
-    R r = readlane_r(a[0], l);
-#pragma unroll
-    for (int c = 1; c < C; ++c) {
-        const R t = readlane_r(a[c], l);
-        r = (idx == c) ? t : r;
-    }
-    return r;
-}
-
 // The same wave-uniform (s) or per-lane (v) integer, taken by the
 // compiler as produced anew where this is called (an empty asm statement,
 // no instruction).  Inside a step loop, masks derived from it are then
@@ -300,7 +285,7 @@ __device__ __forceinline__ void tile_barrier()
 template <typename R, int C, int KIND, bool NEG, bool RING, bool WIN, bool MW, bool EDGE>
 __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                                           int tile, int w, int G_, int64_t block, int T,
-                                          bool ownsProbe, R *__restrict__ xbuf)
+                                          R *__restrict__ xbuf)
 {
     const int G = MW ? G_ : 1;          // one-wave tiles carry no refresh code
     // The full step's single-cell updates (source, end nodes, probe reads)
@@ -654,12 +639,6 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
                 Es[c] = fmad(Dc[c], ce[c], -(hb * sums[c]));
         }
     };
-
-    // Whether this wave owns a probe comes with the tile reference (set on
-    // the host from the same owned ranges).  What the full step alone needs
-    // (the probe cells, the mask of owned probes) it computes itself: a
-    // value computed before the choice of loop stays live across the
-    // interior loop, which has no registers to spare.
 
     // Physical E = E* + beta Bbar at the owned probes, for time n-1/2
     // (E* = E~ / S).  Lane q of the probe table describes probe q: plc =
@@ -1135,7 +1114,6 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
             record(steps + 1, ec.plc, ec.prow, ec.pmask);
         }
     };
-    (void)ownsProbe;
     steps_loop(std::integral_constant<bool, EDGE>{});
 
     if (lane >= own_l && lane < own_r) {
@@ -1220,18 +1198,14 @@ __attribute__((amdgpu_waves_per_eu(occupancy_target<R, C, KIND, MW>()))) void k_
     const bool edge = full_step_wave<C, RING, MW>(rd, ref.tile, w, G, owns_probe);
     if (rd->neg) {
         if (edge)
-            tile_body<R, C, KIND, true, RING, WIN, MW, true>(rd, ref.tile, w, G, block, T,
-                                                             owns_probe, xbuf);
+            tile_body<R, C, KIND, true, RING, WIN, MW, true>(rd, ref.tile, w, G, block, T, xbuf);
         else
-            tile_body<R, C, KIND, true, RING, WIN, MW, false>(rd, ref.tile, w, G, block, T,
-                                                              owns_probe, xbuf);
+            tile_body<R, C, KIND, true, RING, WIN, MW, false>(rd, ref.tile, w, G, block, T, xbuf);
     } else {
         if (edge)
-            tile_body<R, C, KIND, false, RING, WIN, MW, true>(rd, ref.tile, w, G, block, T,
-                                                              owns_probe, xbuf);
+            tile_body<R, C, KIND, false, RING, WIN, MW, true>(rd, ref.tile, w, G, block, T, xbuf);
         else
-            tile_body<R, C, KIND, false, RING, WIN, MW, false>(rd, ref.tile, w, G, block, T,
-                                                               owns_probe, xbuf);
+            tile_body<R, C, KIND, false, RING, WIN, MW, false>(rd, ref.tile, w, G, block, T, xbuf);
     }
 }
 
