@@ -749,8 +749,13 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                     std::max<int64_t>(2, (span + T - 1) / T) + 1, G.nblocks);
                 if (nb < 1)
                     continue;
+                // a lone run is timed from the middle of its run: its early
+                // blocks (the source still on) are not typical of it; a
+                // batch from its start, where every run is live
+                const int64_t b0 = G.members.size() == 1
+                                       ? std::max<int64_t>(0, (G.nblocks - nb) / 2) : 0;
                 double upd = 0.0;
-                for (int64_t b = 1; b < nb; ++b)
+                for (int64_t b = b0 + 1; b < b0 + nb; ++b)
                     for (size_t m = 0; m < G.members.size() && G.blocks_of[m] > b; ++m) {
                         const RunHost &r = runs[G.members[m]];
                         upd += (double)r.p.nz *
@@ -768,9 +773,9 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                 if ((e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + G.prep_off),
                                      (int)G.members.size(), G.max_field, G.precision,
                                      stream)) ||
-                    (e = launch(0)) || (e = hipEventRecord(t0, stream)))
+                    (e = launch(b0)) || (e = hipEventRecord(t0, stream)))
                     return hip_fail(e, "autotune trial");
-                for (int64_t b = 1; b < nb; ++b)
+                for (int64_t b = b0 + 1; b < b0 + nb; ++b)
                     if ((e = launch(b)))
                         return hip_fail(e, "autotune trial");
                 float ms = 0.f;
