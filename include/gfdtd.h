@@ -308,8 +308,9 @@ gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
  * valid (cells per lane in {4, 8, 12, 16}, steps per launch in {8, 16, 24,
  * 32, 48, 64}, 1 or 4 waves per tile off rings) on the prepared runs over
  * about trial_blocks * 48 steps (trial_blocks 0 = 4; eight times that for a
- * group under 4M cells, whose launches are short), and keep the fastest per
- * cell-update; results of a pass do not depend on the choice.  Choices are cached in the process by precision, kind, sign
+ * group under 4M cells, whose launches are short; from the middle of the
+ * run for a group of one run, from the start otherwise), and keep the
+ * fastest per cell-update; results of a pass do not depend on the choice.  Choices are cached in the process by precision, kind, sign
  * mix and the size scales of the group.  Writes the first group's choice to
  * *chosen (may be NULL).  Synchronous; leaves the fields to be re-zeroed by
  * the next gfdtd_batch_run.
