@@ -199,11 +199,28 @@ double spectral_radius(double n2, double S, double beta, int kind,
 // 30 quantiles between them.
 gfdtd_status preflight(const gfdtd_problem *p, double *growth)
 {
-    std::vector<double> n2(p->nz);
-    for (int64_t i = 0; i < p->nz; ++i)
-        n2[i] = p->eps_rest[i] * p->mu_rest[i];
+    // The distinct products, collected in one pass while there are at most
+    // 32 of them (piecewise-constant profiles: no sort of the whole grid),
+    // else sorted and deduplicated.
+    std::vector<double> n2;
+    bool few = true;
+    auto add = [&](double v) {
+        if (few && std::find(n2.begin(), n2.end(), v) == n2.end()) {
+            n2.push_back(v);
+            few = n2.size() <= 32;
+        }
+    };
+    for (int64_t i = 0; i < p->nz && few; ++i)
+        add(p->eps_rest[i] * p->mu_rest[i]);
     if (p->flags & GFDTD_FLAG_TIME_WINDOW)
-        n2.push_back(p->eps_bg * p->mu_bg);
+        add(p->eps_bg * p->mu_bg);
+    if (!few) {
+        n2.resize(p->nz);
+        for (int64_t i = 0; i < p->nz; ++i)
+            n2[i] = p->eps_rest[i] * p->mu_rest[i];
+        if (p->flags & GFDTD_FLAG_TIME_WINDOW)
+            n2.push_back(p->eps_bg * p->mu_bg);
+    }
     std::sort(n2.begin(), n2.end());
     n2.erase(std::unique(n2.begin(), n2.end()), n2.end());
     std::vector<double> pick;

@@ -28,10 +28,13 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -102,23 +105,45 @@ struct Pinned {
     {
         if (bytes <= n)
             return hipSuccess;
+        // grown geometrically from 1 MiB: pinning is slow, and tables grow
+        // as requests join
+        const size_t want = std::max({bytes, 2 * n, size_t(1) << 20});
         if (p)
             (void)hipHostFree(p);
         p = nullptr;
         n = 0;
-        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
         if (e == hipSuccess)
-            n = bytes;
+            n = want;
         return e;
     }
 };
 
-// Reusable pinned blocks in power-of-two size classes (pinning memory is
-// slow; requests come and go).
+// Reusable pinned blocks in power-of-two size classes.  Pinning memory is
+// slow (tens of milliseconds for tens of MiB), and pinning in the progress
+// call would hold up every live request: a class above kSyncBytes is pinned
+// by a helper thread, and the request that needs it waits at the head of
+// the queue meanwhile (try_get reports not ready).
 struct PinnedPool {
+    static constexpr size_t kSyncBytes = size_t(1) << 22;   // 4 MiB
+    std::mutex mu;
+    std::condition_variable cv;
     std::map<size_t, std::vector<void *>> free_;
+    std::deque<size_t> todo;          // classes the helper is to pin
+    std::map<size_t, int> pending;    // blocks being pinned, by class
+    hipError_t failed = hipSuccess;   // the helper's first error
+    bool stop = false;
+    std::thread helper;
+
     ~PinnedPool()
     {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv.notify_all();
+        if (helper.joinable())
+            helper.join();
         for (auto &kv : free_)
             for (void *p : kv.second)
                 (void)hipHostFree(p);
@@ -130,23 +155,64 @@ struct PinnedPool {
             k <<= 1;
         return k;
     }
-    hipError_t get(size_t n, void **p, size_t *cap)
+    void run()
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+            cv.wait(lk, [&] { return stop || !todo.empty(); });
+            if (stop)
+                return;
+            const size_t k = todo.front();
+            todo.pop_front();
+            lk.unlock();
+            void *p = nullptr;
+            const hipError_t e = hipHostMalloc(&p, k, hipHostMallocDefault);
+            lk.lock();
+            pending[k] -= 1;
+            if (e == hipSuccess)
+                free_[k].push_back(p);
+            else if (failed == hipSuccess)
+                failed = e;
+        }
+    }
+    // A block of at least n bytes in *p (capacity *cap) with *ready = true;
+    // or *ready = false while the helper pins one (ask again later).
+    hipError_t try_get(size_t n, void **p, size_t *cap, bool *ready)
     {
         const size_t k = klass(n);
-        auto &v = free_[k];
-        if (!v.empty()) {
-            *p = v.back();
-            v.pop_back();
-            *cap = k;
-            return hipSuccess;
-        }
         *cap = k;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (failed != hipSuccess)
+                return failed;
+            auto &v = free_[k];
+            if (!v.empty()) {
+                *p = v.back();
+                v.pop_back();
+                *ready = true;
+                return hipSuccess;
+            }
+            if (k > kSyncBytes) {
+                if (pending[k] == 0) {
+                    pending[k] += 1;
+                    todo.push_back(k);
+                    if (!helper.joinable())
+                        helper = std::thread(&PinnedPool::run, this);
+                    cv.notify_one();
+                }
+                *ready = false;
+                return hipSuccess;
+            }
+        }
+        *ready = true;
         return hipHostMalloc(p, k, hipHostMallocDefault);
     }
     void put(void *p, size_t cap)
     {
-        if (p)
+        if (p) {
+            std::lock_guard<std::mutex> lk(mu);
             free_[cap].push_back(p);
+        }
     }
 };
 
@@ -166,6 +232,8 @@ struct Request {
     // pinned host block: inputs at admission, results at retirement
     void *host = nullptr;
     size_t host_cap = 0;
+    size_t host_bytes = 0;           // 0 until laid out (host_layout)
+    size_t h_eps = 0, h_mu = 0, h_pr = 0, h_om = 0, h_id = 0, h_ib = 0, h_desc = 0;
     size_t h_dft = 0, h_trace = 0, h_d = 0, h_b = 0;
     hipEvent_t done_ev = nullptr;
     int32_t status = GFDTD_OK;
@@ -395,11 +463,55 @@ struct Server {
     }
 
     // Admit waiting requests in arrival order while they fit.
+    // Offsets of a request's pinned block: inputs (rest profile, probes,
+    // frequencies, initial fields, descriptors) and results (spectra,
+    // trace, final fields).
+    static void host_layout(Request *rq)
+    {
+        const RunHost &r = rq->r;
+        const gfdtd_problem &p = r.p;
+        const RunLayout &L = r.L;
+        const size_t nz = (size_t)p.nz;
+        const size_t w = p.precision == GFDTD_F32 ? 4 : 8;
+        size_t o = 0;
+        rq->h_eps = o;  o += align256(nz * 8);
+        rq->h_mu = o;   o += align256(nz * 8);
+        rq->h_pr = o;   o += align256(std::max<size_t>(r.probes.size(), 1) * 8);
+        rq->h_om = o;   o += align256(std::max<size_t>(r.omegas.size(), 1) * 8);
+        rq->h_id = o;   o += L.has_init_d ? align256(nz * 8) : 0;
+        rq->h_ib = o;   o += L.has_init_b ? align256(nz * 8) : 0;
+        rq->h_desc = o; o += align256(sizeof(RunDesc) + sizeof(PrepDesc) + sizeof(DftDesc));
+        rq->h_dft = o;  o += align256((size_t)std::max(p.nprobe * p.nfreq, 1) * 16);
+        rq->h_trace = o;
+        if (p.flags & GFDTD_FLAG_RECORD_TRACE)
+            o += align256((size_t)std::max<int64_t>((int64_t)p.nprobe * r.steps, 1) * 8);
+        rq->h_d = o;
+        rq->h_b = o;
+        if (p.flags & GFDTD_FLAG_KEEP_FIELDS) {
+            o += align256(nz * w);
+            rq->h_b = o;
+            o += align256(nz * w);
+        }
+        rq->host_bytes = o;
+    }
+
     gfdtd_status admit()
     {
         hipError_t e;
         while (!queue.empty() && (int)live.size() < max_slots) {
             Request *rq = reqs[queue.front()].get();
+            // its pinned block (inputs now, results at retirement) first:
+            // a large one is pinned by a helper thread meanwhile
+            if (!rq->host) {
+                if (!rq->host_bytes)
+                    host_layout(rq);
+                bool ready = false;
+                if ((e = pins.try_get(rq->host_bytes, &rq->host, &rq->host_cap, &ready)))
+                    return hip_fail(e, "pinned host buffer");
+                if (!ready)
+                    break;
+                rq->pins = &pins;
+            }
             if (cap_tiles[rq->group] + rq->ntiles_cap > tile_cap)
                 break;
             size_t off;
@@ -431,34 +543,13 @@ struct Server {
                     return hip_fail(e, "order memory reuse");
             released[rq->group].clear();
 
-            // pinned buffer: inputs now, results at retirement
+            // the pinned block's inputs
             RunHost &r = rq->r;
             const gfdtd_problem &p = r.p;
             const size_t nz = (size_t)p.nz;
-            const size_t w = p.precision == GFDTD_F32 ? 4 : 8;
-            size_t o = 0;
-            const size_t h_eps = o;  o += align256(nz * 8);
-            const size_t h_mu = o;   o += align256(nz * 8);
-            const size_t h_pr = o;   o += align256(std::max<size_t>(r.probes.size(), 1) * 8);
-            const size_t h_om = o;   o += align256(std::max<size_t>(r.omegas.size(), 1) * 8);
-            const size_t h_id = o;   o += L.has_init_d ? align256(nz * 8) : 0;
-            const size_t h_ib = o;   o += L.has_init_b ? align256(nz * 8) : 0;
-            const size_t h_desc = o; o += align256(sizeof(RunDesc) + sizeof(PrepDesc) +
-                                                   sizeof(DftDesc));
-            rq->h_dft = o;   o += align256((size_t)std::max(p.nprobe * p.nfreq, 1) * 16);
-            rq->h_trace = o;
-            if (p.flags & GFDTD_FLAG_RECORD_TRACE)
-                o += align256((size_t)std::max<int64_t>((int64_t)p.nprobe * r.steps, 1) * 8);
-            rq->h_d = o;
-            rq->h_b = o;
-            if (p.flags & GFDTD_FLAG_KEEP_FIELDS) {
-                o += align256(nz * w);
-                rq->h_b = o;
-                o += align256(nz * w);
-            }
-            if ((e = pins.get(o, &rq->host, &rq->host_cap)))
-                return hip_fail(e, "pinned host buffer");
-            rq->pins = &pins;
+            const size_t h_eps = rq->h_eps, h_mu = rq->h_mu, h_pr = rq->h_pr,
+                         h_om = rq->h_om, h_id = rq->h_id, h_ib = rq->h_ib,
+                         h_desc = rq->h_desc;
             char *h = static_cast<char *>(rq->host);
             std::memcpy(h + h_eps, r.eps.data(), nz * 8);
             std::memcpy(h + h_mu, r.mu.data(), nz * 8);
