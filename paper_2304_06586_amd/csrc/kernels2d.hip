@@ -147,11 +147,11 @@ __device__ __forceinline__ int wrapi(int i, int n)
 // Rows r0..r0+C-1 of a column whose lattice has n nodes: vector loads
 // when they all lie on the lattice, else per row with the edge value off
 // the grid (wrapped on a z-ring).
-template <typename R, int C>
+template <typename R, int C, bool INSIDE = false>
 __device__ __forceinline__ void load_rows(const R *__restrict__ col, int r0, int n, int nz,
                                           bool ring, R (&a)[C])
 {
-    if (r0 >= 0 && r0 + C <= n) {
+    if (INSIDE || (r0 >= 0 && r0 + C <= n)) {
         using V = typename RowVec<R, C>::T;
         constexpr int U = sizeof(V) / sizeof(R);
         const V *p = reinterpret_cast<const V *>(col + r0);
@@ -239,17 +239,15 @@ constexpr int halo_rows(int T) { return (3 * T + 3) / 4 * 4; }
 // j + 1, and every stage needs two columns before its first valid one
 // (its carried E*/H* terms), so the march starts T + 1 columns before the
 // chunk and runs T - 1 columns past it.
-template <typename R, int C, bool TE, bool COLA, int T>
-__global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int par, int xch,
-                                                int nstrips, int waves, int blocks)
+//
+// EDGE: the wave holds an end of the z lattices, rows off them, the source
+// row or a probe; every other wave runs a march compiled without that code
+// (no source, end or probe updates, no edge values, vector loads only).
+template <typename R, int C, bool TE, bool COLA, int T, bool EDGE>
+__device__ __forceinline__ void step2d_wave(const Run2D &rd, int64_t n0, int par, int xch,
+                                            int nstrips, int w)
 {
     const int lane = threadIdx.x & 63;
-    // each XCD (blocks b = x mod 8) takes a contiguous range of wave ids
-    const int b = blockIdx.x;
-    const int lb = (b & 7) * (blocks >> 3) + (b >> 3);
-    const int w = lb * 4 + (int)(threadIdx.x >> 6);
-    if (w >= waves)
-        return;
     constexpr int H = halo_rows(T);
     constexpr int STRIDE = 64 * C - 2 * H;
     const int s = w % nstrips;
@@ -273,9 +271,9 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
     // the rows a wave holds that need the source, the ends or the grid-edge
     // values (halo rows included: later stages read them)
     const int src_row = (int)rd.src_row;
-    const bool src_here = src_row >= z0 && src_row < z0 + 64 * C;
-    const bool lo_edge = !ring && z0 < 0;
-    const bool hi_edge_d = !ring && z0 + 64 * C > nz - 1;
+    const bool src_here = EDGE && src_row >= z0 && src_row < z0 + 64 * C;
+    const bool lo_edge = EDGE && !ring && z0 < 0;
+    const bool hi_edge_d = EDGE && !ring && z0 + 64 * C > nz - 1;
 
     // per-stage constants: material coefficients (z only), source sample,
     // end coefficients, the shift for the probes' eps
@@ -330,7 +328,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
     auto colp = [&](const R *base, int i) { return base + (int64_t)wrapc(i) * ld; };
 
     uint64_t own = 0;                        // probes this wave records
-    for (int q = 0; q < rd.nprobe; ++q) {
+    for (int q = 0; EDGE && q < rd.nprobe; ++q) {
         const int64_t x = rd.px[q], z = rd.pz[q];
         if (z >= vlo && z < vhi && x >= i0 && x < i1)
             own |= 1ull << q;
@@ -434,7 +432,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
                 if (r0 + q < 0)
                     a[q] = e;
         }
-        if (!ring && z0 + 64 * C > nlat) {
+        if (EDGE && !ring && z0 + 64 * C > nlat) {
             const int off = nlat - 1 - z0;
             const int lr = off / C, qr = off % C;
             R v = a[0];
@@ -463,9 +461,9 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
     // loads of stage 0's first column: TE D, B at k + 1 and C at k; TM D, B
     // at k and C at k + 1
     R Ld[C], Lb[C], Lc[C];
-    load_rows<R, C>(colp(Din, TE ? kbeg + 1 : kbeg), r0, nz, nz, ring, Ld);
-    load_rows<R, C>(colp(Bin, TE ? kbeg + 1 : kbeg), r0, nh, nz, ring, Lb);
-    load_rows<R, C>(colp(Cin, TE ? kbeg : kbeg + 1), r0, nc, nz, ring, Lc);
+    load_rows<R, C, !EDGE>(colp(Din, TE ? kbeg + 1 : kbeg), r0, nz, nz, ring, Ld);
+    load_rows<R, C, !EDGE>(colp(Bin, TE ? kbeg + 1 : kbeg), r0, nh, nz, ring, Lb);
+    load_rows<R, C, !EDGE>(colp(Cin, TE ? kbeg : kbeg + 1), r0, nc, nz, ring, Lc);
     R dd[C], t1[C], t2[C];
     for (int k = kbeg; k <= kend; ++k) {
         R inD[C], inB[C], inC[C];
@@ -477,9 +475,9 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
         }
         if (k < kend) {            // next column's loads, in flight meanwhile
             const int kn = k + 1;
-            load_rows<R, C>(colp(Din, TE ? kn + 1 : kn), r0, nz, nz, ring, Ld);
-            load_rows<R, C>(colp(Bin, TE ? kn + 1 : kn), r0, nh, nz, ring, Lb);
-            load_rows<R, C>(colp(Cin, TE ? kn : kn + 1), r0, nc, nz, ring, Lc);
+            load_rows<R, C, !EDGE>(colp(Din, TE ? kn + 1 : kn), r0, nz, nz, ring, Ld);
+            load_rows<R, C, !EDGE>(colp(Bin, TE ? kn + 1 : kn), r0, nh, nz, ring, Lb);
+            load_rows<R, C, !EDGE>(colp(Cin, TE ? kn : kn + 1), r0, nc, nz, ring, Lc);
         }
         R nxt[T][C], nxt2[T][C];   // delayed inputs for the next column
 #pragma unroll
@@ -605,6 +603,51 @@ __global__ __launch_bounds__(256) void k_step2d(const Run2D rd, int64_t n0, int 
     }
 }
 
+// Waves per SIMD the register allocation must allow: FP32 at 2 cells per
+// lane and 3 steps a launch fits 4 without spilling (left to itself the
+// compiler takes one register more); elsewhere its own choice (1: no
+// constraint).
+template <typename R, int C, int T>
+constexpr int occupancy2d()
+{
+    return (sizeof(R) == 4 && C == 2 && T == 3) ? 4 : 1;
+}
+
+template <typename R, int C, bool TE, bool COLA, int T>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(occupancy2d<R, C, T>()))) void k_step2d(
+    const Run2D rd, int64_t n0, int par, int xch, int nstrips, int waves, int blocks)
+{
+    // each XCD (blocks b = x mod 8) takes a contiguous range of wave ids
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * (blocks >> 3) + (b >> 3);
+    const int w = lb * 4 + (int)(threadIdx.x >> 6);
+    if (w >= waves)
+        return;
+    // the wave's rows [z0, z0 + 64 C) and columns [i0, i1), as step2d_wave
+    // takes them: it runs the full march if they hold the source row, a row
+    // off any lattice (an end, or a wrap on a ring) or a probe
+    constexpr int H = halo_rows(T);
+    constexpr int STRIDE = 64 * C - 2 * H;
+    const int s = w % nstrips;
+    const int z0 = s * STRIDE - H;
+    const int nlat = (int)(rd.nh < rd.nc ? rd.nh : rd.nc);   // nh <= nc <= nz
+    bool edge = z0 < 0 || z0 + 64 * C > nlat ||
+                (rd.src_row >= z0 && rd.src_row < z0 + 64 * C);
+    if (!edge) {
+        const int vlo = s * STRIDE;
+        const int vhi = vlo + STRIDE < rd.nz ? vlo + STRIDE : (int)rd.nz;
+        const int i0 = (w / nstrips) * xch;
+        const int i1 = i0 + xch < rd.nx ? i0 + xch : (int)rd.nx;
+        for (int q = 0; q < rd.nprobe && !edge; ++q)
+            edge = rd.pz[q] >= vlo && rd.pz[q] < vhi && rd.px[q] >= i0 && rd.px[q] < i1;
+    }
+    if (edge)
+        step2d_wave<R, C, TE, COLA, T, true>(rd, n0, par, xch, nstrips, w);
+    else
+        step2d_wave<R, C, TE, COLA, T, false>(rd, n0, par, xch, nstrips, w);
+}
+
 // Source samples g(n S) and the initial fields of both halves of every
 // ping-pong pair (a plain fill kernel: no memset nodes).
 __global__ __launch_bounds__(256) void k_prep2d(const Run2D *__restrict__ rdp)
@@ -691,8 +734,8 @@ Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch, in
         // a march of T steps starts T + 1 columns early, so deeper blocks
         // want longer marches: at most 8, 16, 16, 32 columns for T = 1..4,
         // fewer when the grid would give under 2048 waves.  Measured on the
-        // 4096 x 4096 grid at 2 cells per lane: FP32 T = 3 best with 16
-        // columns, FP64 T = 4 with 32, one step a launch with 8-16
+        // 4096 x 4096 grid at 2 cells per lane: T = 4 best, FP32 with 16-32
+        // columns, FP64 with 32; one step a launch with 8-16
         static const int cap_of[5] = {8, 8, 16, 16, 32};
         const int64_t x = nx * L.nstrips / 2048;
         const int64_t cap = cap_of[T < 0 ? 0 : (T > 4 ? 4 : T)];

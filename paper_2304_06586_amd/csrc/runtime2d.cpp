@@ -347,8 +347,8 @@ gfdtd_status prepare2d(const gfdtd2d_problem *p, int64_t steps, const gfdtd2d_ex
         return fail(GFDTD_E_INVALID, "block_steps %d needs at most %d cells per lane "
                     "and non-periodic ends", T, narrow);
     if (T == 0)   // several steps a launch where the tiling allows it (measured
-                  // best: FP32 three, FP64 four, both at 2 cells per lane)
-        T = (ring || (C != 0 && C > narrow)) ? 1 : (p->precision == GFDTD_F32 ? 3 : 4);
+                  // best: four, FP32 and FP64, at 2 cells per lane)
+        T = (ring || (C != 0 && C > narrow)) ? 1 : 4;
     Layout2D L = carve2d(p, steps);
     if (!ws || ws_bytes < L.total)
         return fail(GFDTD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, L.total);
