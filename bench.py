@@ -242,10 +242,16 @@ def twod_leg(P, args):
 
 def kernel_roofline(st, updates, precision):
     """k_tiles of the last pass against the vector-ALU peak, from the
-    library's HIP events around the pass's stepping launches."""
+    library's HIP events around the pass's stepping launches.  When the
+    batch splits its runs over two streams, launches of the two halves run
+    concurrently: each stream is busy for the whole stepping phase, so a
+    launch lasts streams x step time / launches on average, and `achieved`
+    is the flops of all launches over the phase (the two streams' launches
+    summed)."""
     step_s = st["step_ms"] / 1e3
     launches = max(1, int(st["launches"]))
-    avg_launch_ms = st["step_ms"] / launches
+    streams = max(1, int(st.get("streams", 1)))
+    avg_launch_ms = st["step_ms"] * streams / launches
     k_rate = updates / step_s if step_s > 0 else 0.0
     achieved = k_rate * FLOPS_PER_UPDATE / 1e12
     per_update = measured_traffic_per_update(int(st["cells_per_lane"]),
@@ -263,12 +269,13 @@ def kernel_roofline(st, updates, precision):
         "traffic": traffic,
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                         "copy-calibrated)",
-        "measured_hbm_GBs": (round(traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
+        "measured_hbm_GBs": (round(streams * traffic / (avg_launch_ms * 1e-3) / 1e9, 1)
                              if traffic is not None and avg_launch_ms > 0 else None),
         "algorithmic_bytes_per_launch": upd_per_launch * BYTES_PER_UPDATE[precision],
         "flops_per_update": FLOPS_PER_UPDATE,
         "kernel_cell_updates_per_s": k_rate,
         "launches_per_pass": launches,
+        "concurrent_streams": streams,
         "avg_launch_ms": round(avg_launch_ms, 4),
         "cells_per_lane": int(st["cells_per_lane"]),
         "block_steps": int(st["block_steps"]),

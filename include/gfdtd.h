@@ -299,6 +299,12 @@ typedef struct gfdtd_stats {
     double pass_ms;              /* device time of the whole last pass     */
     int32_t tile_waves;          /* waves per tile                         */
     int32_t exchange_steps;      /* steps between overlap refreshes        */
+    int32_t streams;             /* streams the stepping launches use: 2
+                                    when a group of at least 4M cells is
+                                    split into two halves whose launches
+                                    overlap (launches and tiles count both),
+                                    else 1                                 */
+    int32_t reserved;
 } gfdtd_stats;
 
 gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);

@@ -361,6 +361,32 @@ size_t table_bytes(int nruns, int64_t max_tiles)
 // one owned lane).
 int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 
+// Runs of one (precision, kind, ends) group in launch order, longest first
+// (stable), split into the parts whose launches go to separate streams.  A
+// launch ends with a drain in which its last waves leave most of the GPU
+// idle, and the next launch of the same runs cannot start before it ends.
+// A large group is therefore split into two halves (alternate runs, so both
+// keep long runs to the end), each with its own tables, whose launches are
+// issued to two streams: one half's waves fill the other's drain.  Measured
+// on 4096 crystal runs: FP32 3.42e12 -> 3.71e12 cell-updates/s, FP64
+// 2.14e12 -> 2.22e12; four parts were slower than two.  Groups under
+// kPartCells cells stay whole.
+constexpr int kParts = 2;
+constexpr int64_t kPartCells = (int64_t)4 << 20;
+
+template <typename StepsOf>
+std::vector<std::vector<int>> stream_parts(std::vector<int> members, int64_t cells,
+                                           bool allow, StepsOf steps_of)
+{
+    std::stable_sort(members.begin(), members.end(),
+                     [&](int a, int b) { return steps_of(a) > steps_of(b); });
+    const int n = (allow && members.size() >= 2 && cells >= kPartCells) ? kParts : 1;
+    std::vector<std::vector<int>> parts(n);
+    for (size_t m = 0; m < members.size(); ++m)
+        parts[m % n].push_back(members[m]);
+    return parts;
+}
+
 // --------------------------------------------------------------- tiling
 
 // Tiling defaults from measurements on MI355X (full-occupancy launches of
@@ -537,11 +563,19 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         choose_tiling(G.precision, ex, max_steps, cells, G.ring, G.C, G.T, G.Gw, G.K);
         for (int i : G.members)
             runs[i].T = G.T;
-        int64_t maxt = 0;
-        for (int i : G.members)
-            maxt += max_tiles_of(runs[i].p.nz);
-        G.table_off = cv.take(table_bytes((int)G.members.size(), maxt));
-        groups.push_back(G);
+        // the allocation-free entry point has no second stream
+        auto parts = stream_parts(G.members, cells, !no_alloc,
+                                  [&](int i) { return runs[i].steps; });
+        for (size_t q = 0; q < parts.size(); ++q) {
+            Group H = G;
+            H.members = parts[q];
+            H.part = (int)q;
+            int64_t maxt = 0;
+            for (int i : H.members)
+                maxt += max_tiles_of(runs[i].p.nz);
+            H.table_off = cv.take(table_bytes((int)H.members.size(), maxt));
+            groups.push_back(H);
+        }
     }
     if (cv.off > ws_bytes)
         return fail(GFDTD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, cv.off);
@@ -610,6 +644,13 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
     if ((e = hipEventCreate(&ev[0])) || (e = hipEventCreate(&ev[1])) ||
         (e = hipEventCreate(&ev[2])) || (e = hipEventCreate(&ev[3])))
         return hip_fail(e, "create events");
+    bool two = false;
+    for (auto &G : groups)
+        two = two || G.part > 0;
+    if (two && ((e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking)) ||
+                (e = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming)) ||
+                (e = hipEventCreateWithFlags(&join_ev, hipEventDisableTiming))))
+        return hip_fail(e, "create second stream");
     if (use_graph == 1 || (use_graph < 0 && auto_graph()))
         return build_graphs();
     return GFDTD_OK;
@@ -997,25 +1038,43 @@ gfdtd_status Batch::enqueue_zero(hipStream_t s)
     return GFDTD_OK;
 }
 
-gfdtd_status Batch::enqueue_steps(hipStream_t s)
+// Stepping launches of every group, block by block.  With `fork` (and a
+// second stream), groups of part 1 launch on the second stream, which
+// starts after the work already on `s` and is joined back to `s` at the end;
+// otherwise everything goes to `s` in the same order.
+gfdtd_status Batch::enqueue_steps(hipStream_t s, bool fork)
 {
+    hipError_t e;
+    fork = fork && side;
+    if (fork && ((e = hipEventRecord(fork_ev, s)) || (e = hipStreamWaitEvent(side, fork_ev, 0))))
+        return hip_fail(e, "fork second stream");
     int64_t nb = 0;
     for (auto &G : groups)
         nb = std::max(nb, G.nblocks);
-    for (int64_t b = 0; b < nb; ++b)
+    gfdtd_status st = GFDTD_OK;
+    for (int64_t b = 0; b < nb && st == GFDTD_OK; ++b)
         for (auto &G : groups) {
             if (b >= G.nblocks)
                 continue;
+            hipStream_t gs = (fork && G.part > 0) ? side : s;
             for (int w = 0; w < (G.has_window ? 2 : 1); ++w) {
-                hipError_t e = launch_tiles(G.precision, G.kind, G.ring, w == 1, G.C, G.Gw,
-                                            reinterpret_cast<const RunDesc *>(ws + G.runs_off),
-                                            reinterpret_cast<const TileRef *>(ws + G.tiles_off),
-                                            b, G.T, live_tiles(G, b), s);
-                if (e)
-                    return hip_fail(e, "launch step kernel");
+                e = launch_tiles(G.precision, G.kind, G.ring, w == 1, G.C, G.Gw,
+                                 reinterpret_cast<const RunDesc *>(ws + G.runs_off),
+                                 reinterpret_cast<const TileRef *>(ws + G.tiles_off), b, G.T,
+                                 live_tiles(G, b), gs);
+                if (e) {
+                    st = hip_fail(e, "launch step kernel");
+                    break;
+                }
             }
+            if (st != GFDTD_OK)
+                break;
         }
-    return GFDTD_OK;
+    // join even after a failed launch, so `s` orders everything issued
+    if (fork && ((e = hipEventRecord(join_ev, side)) || (e = hipStreamWaitEvent(s, join_ev, 0))) &&
+        st == GFDTD_OK)
+        return hip_fail(e, "join second stream");
+    return st;
 }
 
 gfdtd_status Batch::enqueue_dft(hipStream_t s)
@@ -1038,7 +1097,7 @@ gfdtd_status Batch::build_graphs()
         if ((e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed)))
             return hip_fail(e, "begin capture");
         gfdtd_status st = k == 0 ? enqueue_zero(cap_stream)
-                          : k == 1 ? enqueue_steps(cap_stream)
+                          : k == 1 ? enqueue_steps(cap_stream, false)
                                    : enqueue_dft(cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap_stream, &g);
@@ -1071,7 +1130,7 @@ gfdtd_status Batch::run()
     if (graph_on) {
         if ((e = hipGraphLaunch(execs[1], stream)))
             return hip_fail(e, "launch step graph");
-    } else if ((st = enqueue_steps(stream)) != GFDTD_OK) {
+    } else if ((st = enqueue_steps(stream, true)) != GFDTD_OK) {
         return st;
     }
     if (ev[2])
@@ -1201,6 +1260,9 @@ void Batch::stats(gfdtd_stats *s) const
     s->tile_waves = groups.empty() ? 0 : groups[0].Gw;
     s->exchange_steps = groups.empty() ? 0 : groups[0].K;
     s->graph = graph_on ? 1 : 0;
+    // a captured pass keeps every launch on one stream
+    s->streams = (side && !graph_on) ? 2 : 1;
+    s->reserved = 0;
     s->launches = launches;
     s->tiles = tiles_total;
     s->cell_updates = cell_updates;
@@ -1220,6 +1282,8 @@ Batch::~Batch()
     // kernels or uploads of this batch may still be running on its stream
     // (a destroy without collect, or an error path): the caller frees the
     // workspace, and this object the upload sources, right after
+    if (side)
+        (void)hipStreamSynchronize(side);
     if (stream)
         (void)hipStreamSynchronize(stream);
     for (int k = 0; k < 3; ++k) {
@@ -1230,6 +1294,12 @@ Batch::~Batch()
     }
     if (cap_stream)
         (void)hipStreamDestroy(cap_stream);
+    if (side)
+        (void)hipStreamDestroy(side);
+    if (fork_ev)
+        (void)hipEventDestroy(fork_ev);
+    if (join_ev)
+        (void)hipEventDestroy(join_ev);
     for (auto &x : ev)
         if (x)
             (void)hipEventDestroy(x);
@@ -1292,8 +1362,8 @@ gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
     if (!bytes || count < 0 || (count > 0 && (!probs || !steps)))
         return fail(GFDTD_E_INVALID, "bad arguments");
     Carver cv;
-    int64_t maxt[kGroups] = {};
-    int nr[kGroups] = {};
+    std::vector<int> members[kGroups];
+    int64_t cells[kGroups] = {};
     for (int i = 0; i < count; ++i) {
         gfdtd_status st = validate(&probs[i], steps[i]);
         if (st != GFDTD_OK)
@@ -1301,12 +1371,21 @@ gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
         RunLayout L;
         carve_run(cv, &probs[i], steps[i], L);
         const int g = group_of(probs[i].precision, probs[i].kind, probs[i].abc);
-        maxt[g] += max_tiles_of(probs[i].nz);
-        nr[g] += 1;
+        members[g].push_back(i);
+        cells[g] += probs[i].nz;
     }
+    // the tables of every stream part (a batch that keeps a group whole
+    // needs no more than this)
     for (int g = 0; g < kGroups; ++g)
-        if (nr[g])
-            cv.take(table_bytes(nr[g], maxt[g]));
+        for (auto &part : stream_parts(members[g], cells[g], true,
+                                       [&](int i) { return steps[i]; })) {
+            if (part.empty())
+                continue;
+            int64_t maxt = 0;
+            for (int i : part)
+                maxt += max_tiles_of(probs[i].nz);
+            cv.take(table_bytes((int)part.size(), maxt));
+        }
     *bytes = cv.off;
     return GFDTD_OK;
 }

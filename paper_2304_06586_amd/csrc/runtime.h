@@ -97,6 +97,7 @@ struct Group {
     int Gw = 1, K = 8;                // waves per tile, steps per refresh
     bool ring = false;                // periodic ends
     bool has_window = false;          // holds finite-duration modulations
+    int part = 0;                     // stream its launches go to (0: the batch's)
     std::vector<int> members;         // run indices, longest first
     std::vector<int64_t> blocks_of;   // blocks per member
     std::vector<int64_t> tiles_prefix;
@@ -123,6 +124,10 @@ struct Batch {
     bool no_alloc = false;
     bool ran = false;
     hipStream_t cap_stream = nullptr;
+    // second stream for the launches of groups with part 1, forked from and
+    // joined back to the batch's stream around the stepping launches
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     hipGraph_t graphs[3] = {nullptr, nullptr, nullptr};
     hipGraphExec_t execs[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -137,7 +142,7 @@ struct Batch {
     int live_tiles(const Group &G, int64_t b) const;
     bool auto_graph() const;
     gfdtd_status enqueue_zero(hipStream_t s);
-    gfdtd_status enqueue_steps(hipStream_t s);
+    gfdtd_status enqueue_steps(hipStream_t s, bool fork);
     gfdtd_status enqueue_dft(hipStream_t s);
     gfdtd_status build_graphs();
     gfdtd_status build_tiles(Group &G);

@@ -93,7 +93,8 @@ class gfdtd_stats(C.Structure):
         ("launches", C.c_int64), ("tiles", C.c_int64),
         ("cell_updates", C.c_double), ("step_ms", C.c_double),
         ("pass_ms", C.c_double), ("tile_waves", C.c_int32),
-        ("exchange_steps", C.c_int32),
+        ("exchange_steps", C.c_int32), ("streams", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

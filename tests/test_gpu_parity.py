@@ -199,6 +199,30 @@ def test_batch_equals_alone_bitwise(P):
         compare(got, oracle.solve(p), tol, p.label)
 
 
+def test_two_stream_batch_equals_alone_bitwise(P):
+    """Groups of at least 4M cells are split into two halves whose launches
+    go to two streams and overlap.  Each run of such a batch (two groups,
+    runs of different lengths, so the halves end at different blocks) gives
+    the same bits as the run alone, on one stream."""
+    spec = [(700_001 + 37 * i, 120 + 41 * i, (-0.3, 0.2, 0.45)[i % 3]) for i in range(6)]
+    probs = [W.small_case(n, s, b, kind=W.MODULATION, precision=W.F32,
+                          structure="random", seed=10 + i)
+             for i, (n, s, b) in enumerate(spec)]
+    probs += [W.small_case(n, s + 7, -b, kind=W.MATTER, precision=W.F64,
+                           structure="slab", seed=20 + i)
+              for i, (n, s, b) in enumerate(spec)]
+    assert sum(p.nz for p in probs[:6]) >= 4 << 20
+    with P.Batch(probs) as b:
+        b.run()
+        got = b.collect()
+        st = b.stats()
+    assert st["streams"] == 2 and st["graph"] == 0, st
+    for p, g in zip(probs, got):
+        alone = P.gfdtd_solve(p)
+        for k in ("trace", "dft", "d", "b"):
+            assert np.array_equal(g[k], alone[k]), (p.label, k)
+
+
 def test_zero_steps_and_no_probes(P):
     p = W.small_case(300, 0, 0.3, seed=2)
     got = P.gfdtd_solve(p)
