@@ -316,7 +316,10 @@ gfdtd_status gfdtd_batch_stats(const gfdtd_batch *b, gfdtd_stats *s);
  * about trial_blocks * 48 steps (trial_blocks 0 = 4; eight times that for a
  * group under 4M cells, whose launches are short; from the middle of the
  * run for a group of one run, from the start otherwise), and keep the
- * fastest per cell-update; results of a pass do not depend on the choice.  Choices are cached in the process by precision, kind, sign
+ * fastest per cell-update.  A group split over two streams (see streams in
+ * gfdtd_stats) is timed with both halves' launches on their streams, as a
+ * pass issues them, and both take the same choice.  Results of a pass do
+ * not depend on the choice.  Choices are cached in the process by precision, kind, sign
  * mix and the size scales of the group.  Writes the first group's choice to
  * *chosen (may be NULL).  Synchronous; leaves the fields to be re-zeroed by
  * the next gfdtd_batch_run.

@@ -398,9 +398,13 @@ void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
                    int64_t total_cells, bool ring, int &C, int &T, int &G, int &K)
 {
     const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
+    // large groups run on two streams, where the wider FP64 tiles win: the
+    // full 4096-run crystal pass at C = 16 ran 2 % faster than at C = 12
+    // (2.32e12 against 2.28e12, three passes each), although with every run
+    // live on one stream C = 12 was 5 % faster
+    (void)precision;
     const bool small = total_cells < (int64_t)4 << 20;
-    C = (ex && ex->cells_per_lane) ? ex->cells_per_lane
-                                   : (small ? 4 : (precision == GFDTD_F32 ? 16 : 12));
+    C = (ex && ex->cells_per_lane) ? ex->cells_per_lane : (small ? 4 : 16);
     if (variant == GFDTD_VARIANT_STEP)
         T = 1;
     else if (ex && ex->block_steps > 0)
@@ -751,28 +755,84 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
     if ((e = hipEventCreate(&evs.t0)) || (e = hipEventCreate(&evs.t1)))
         return hip_fail(e, "create events");
     hipEvent_t t0 = evs.t0, t1 = evs.t1;
-    for (auto &G : groups) {
+    // The parts of one (precision, kind, ends) group are consecutive in
+    // `groups` and take one choice, timed with their launches on their own
+    // streams as a pass issues them (with two streams, larger tiles win:
+    // the other stream fills each launch's drain).
+    for (size_t f0 = 0; f0 < groups.size();) {
+        size_t f1 = f0 + 1;
+        while (f1 < groups.size() && groups[f1].part > 0)
+            ++f1;
+        std::vector<Group *> fam;
+        for (size_t g = f0; g < f1; ++g)
+            fam.push_back(&groups[g]);
+        f0 = f1;
+        const Group &G = *fam[0];
+        const bool split = side != nullptr && fam.size() > 1;
         double cells = 0.0, steps = 0.0;
         int neg = 0;
-        for (int i : G.members) {
-            cells += (double)runs[i].p.nz;
-            steps = std::max(steps, (double)runs[i].steps);
-            neg |= runs[i].p.beta < 0.0 ? 2 : 1;
+        size_t nmem = 0;
+        for (Group *H : fam) {
+            for (int i : H->members) {
+                cells += (double)runs[i].p.nz;
+                steps = std::max(steps, (double)runs[i].steps);
+                neg |= runs[i].p.beta < 0.0 ? 2 : 1;
+            }
+            nmem += H->members.size();
         }
         const TuneKey key{G.precision * 4 + G.kind * 2 + (G.ring ? 1 : 0), neg,
-                          ilog2((double)G.members.size()), ilog2(cells), ilog2(steps)};
+                          ilog2((double)nmem), ilog2(cells), ilog2(steps)};
+        auto apply = [&](int C, int T, int Gw) {
+            for (Group *H : fam) {
+                H->C = C;
+                H->T = T;
+                H->Gw = Gw;
+                gfdtd_status s2 = build_tiles(*H);
+                if (s2 != GFDTD_OK)
+                    return s2;
+            }
+            return GFDTD_OK;
+        };
         {
             std::lock_guard<std::mutex> lk(g_tune_mutex);
             auto it = g_tune_cache.find(key);
             if (it != g_tune_cache.end()) {
-                G.C = it->second.C;
-                G.T = it->second.T;
-                G.Gw = it->second.G;
-                if ((st = build_tiles(G)) != GFDTD_OK)
+                if ((st = apply(it->second.C, it->second.T, it->second.G)) != GFDTD_OK)
                     return st;
                 continue;
             }
         }
+        auto fork = [&]() {
+            if (!split)
+                return hipSuccess;
+            hipError_t x = hipEventRecord(fork_ev, stream);
+            return x ? x : hipStreamWaitEvent(side, fork_ev, 0);
+        };
+        auto join = [&]() {
+            if (!split)
+                return hipSuccess;
+            hipError_t x = hipEventRecord(join_ev, side);
+            return x ? x : hipStreamWaitEvent(stream, join_ev, 0);
+        };
+        // blocks [from, to) of every part, in the order a pass issues them
+        auto blocks = [&](int64_t from, int64_t to) {
+            for (int64_t b = from; b < to; ++b)
+                for (Group *H : fam) {
+                    if (b >= H->nblocks)
+                        continue;
+                    hipStream_t hs = (split && H->part > 0) ? side : stream;
+                    for (int w = 0; w < (H->has_window ? 2 : 1); ++w) {
+                        hipError_t le = launch_tiles(
+                            H->precision, H->kind, H->ring, w == 1, H->C, H->Gw,
+                            reinterpret_cast<const RunDesc *>(ws + H->runs_off),
+                            reinterpret_cast<const TileRef *>(ws + H->tiles_off), b, H->T,
+                            live_tiles(*H, b), hs);
+                        if (le)
+                            return le;
+                    }
+                }
+            return hipSuccess;
+        };
         const int defC = G.C, defT = G.T, defG = G.Gw;
         int bestC = G.C, bestT = G.T, bestG = G.Gw;
         double best = 1e300, def_time = 1e300;
@@ -788,15 +848,16 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                     continue;
                 bool ok = true;
                 TileGeom tg;
-                for (int i : G.members)
-                    ok = ok && run_geometry(runs[i].p, C, T, Gw, G.K, tg);
+                for (Group *H : fam)
+                    for (int i : H->members)
+                        ok = ok && run_geometry(runs[i].p, C, T, Gw, H->K, tg);
                 if (!ok)
                     continue;
-                G.C = C;
-                G.T = T;
-                G.Gw = Gw;
-                if ((st = build_tiles(G)) != GFDTD_OK)
+                if ((st = apply(C, T, Gw)) != GFDTD_OK)
                     return st;
+                int64_t nblocks = 0;
+                for (Group *H : fam)
+                    nblocks = std::max(nblocks, H->nblocks);
                 // every candidate is timed over about the same number of
                 // steps (trial blocks of 48 steps), and a small group (a lone
                 // run: launch-bound, short launches) over at least 1536, so
@@ -804,38 +865,30 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
                 // by fewer, noisier launches; block 0 is not timed
                 const int64_t span = (int64_t)trial * 48 * (cells < 4.0e6 ? 8 : 1);
                 const int64_t nb = std::min<int64_t>(
-                    std::max<int64_t>(2, (span + T - 1) / T) + 1, G.nblocks);
+                    std::max<int64_t>(2, (span + T - 1) / T) + 1, nblocks);
                 if (nb < 1)
                     continue;
                 // a lone run is timed from the middle of its run: its early
                 // blocks (the source still on) are not typical of it; a
                 // batch from its start, where every run is live
-                const int64_t b0 = G.members.size() == 1
-                                       ? std::max<int64_t>(0, (G.nblocks - nb) / 2) : 0;
+                const int64_t b0 = nmem == 1 ? std::max<int64_t>(0, (nblocks - nb) / 2) : 0;
                 double upd = 0.0;
-                for (int64_t b = b0 + 1; b < b0 + nb; ++b)
-                    for (size_t m = 0; m < G.members.size() && G.blocks_of[m] > b; ++m) {
-                        const RunHost &r = runs[G.members[m]];
-                        upd += (double)r.p.nz *
-                               (double)std::min<int64_t>(T, r.steps - b * (int64_t)T);
-                    }
-                auto launch = [&](int64_t b) {
-                    hipError_t le = hipSuccess;
-                    for (int w = 0; w < (G.has_window ? 2 : 1) && !le; ++w)
-                        le = launch_tiles(G.precision, G.kind, G.ring, w == 1, C, Gw,
-                                          reinterpret_cast<const RunDesc *>(ws + G.runs_off),
-                                          reinterpret_cast<const TileRef *>(ws + G.tiles_off),
-                                          b, T, live_tiles(G, b), stream);
-                    return le;
-                };
-                if ((e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + G.prep_off),
-                                     (int)G.members.size(), G.max_field, G.precision,
-                                     stream)) ||
-                    (e = launch(b0)) || (e = hipEventRecord(t0, stream)))
-                    return hip_fail(e, "autotune trial");
-                for (int64_t b = b0 + 1; b < b0 + nb; ++b)
-                    if ((e = launch(b)))
+                for (Group *H : fam)
+                    for (int64_t b = b0 + 1; b < b0 + nb; ++b)
+                        for (size_t m = 0; m < H->members.size() && H->blocks_of[m] > b; ++m) {
+                            const RunHost &r = runs[H->members[m]];
+                            upd += (double)r.p.nz *
+                                   (double)std::min<int64_t>(T, r.steps - b * (int64_t)T);
+                        }
+                for (Group *H : fam)
+                    if ((e = launch_zero(reinterpret_cast<const PrepDesc *>(ws + H->prep_off),
+                                         (int)H->members.size(), H->max_field, H->precision,
+                                         stream)))
                         return hip_fail(e, "autotune trial");
+                if ((e = fork()) || (e = blocks(b0, b0 + 1)) || (e = join()) ||
+                    (e = hipEventRecord(t0, stream)) || (e = fork()) ||
+                    (e = blocks(b0 + 1, b0 + nb)) || (e = join()))
+                    return hip_fail(e, "autotune trial");
                 float ms = 0.f;
                 if ((e = hipEventRecord(t1, stream)) || (e = hipEventSynchronize(t1)) ||
                     (e = hipEventElapsedTime(&ms, t0, t1)))
@@ -857,10 +910,7 @@ gfdtd_status Batch::autotune(int trial, gfdtd_exec *chosen)
             bestT = defT;
             bestG = defG;
         }
-        G.C = bestC;
-        G.T = bestT;
-        G.Gw = bestG;
-        if ((st = build_tiles(G)) != GFDTD_OK)
+        if ((st = apply(bestC, bestT, bestG)) != GFDTD_OK)
             return st;
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         g_tune_cache[key] = {bestC, bestT, bestG};
