@@ -75,9 +75,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# Counter summaries per precision, one per tiling the autotuner picks on the
+# crystal batch (FP64 lands on 12 or 16 cells per lane, about 2 % apart).
 COUNTERS = {
-    W.F32: os.path.join(ROOT, "profiles", "k_tiles_f32_crystals4096_hbm_counters.txt"),
-    W.F64: os.path.join(ROOT, "profiles", "k_tiles_f64_crystals4096_hbm_counters.txt"),
+    W.F32: [os.path.join(ROOT, "profiles", "k_tiles_f32_crystals4096_hbm_counters.txt")],
+    W.F64: [os.path.join(ROOT, "profiles", "k_tiles_f64_crystals4096_hbm_counters.txt"),
+            os.path.join(ROOT, "profiles", "k_tiles_f64_c12_crystals4096_hbm_counters.txt")],
 }
 KERNEL_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels.hip")
 KERNEL2D_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels2d.hip")
@@ -95,20 +98,28 @@ def measured_traffic_per_update(C, T, precision=W.F32):
     the kernel source has changed since they were taken or they were taken
     at another tiling (cells per lane C, steps per launch T)."""
     import hashlib
+    paths = COUNTERS[precision]
+    if isinstance(paths, str):
+        paths = [paths]
     try:
-        kv = {}
-        for line in open(COUNTERS[precision]):
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha:
-            return None
-        if int(kv["cells_per_lane"]) != C or int(kv["block_steps"]) != T:
-            return None
-        return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
-    except (OSError, KeyError, ValueError):
+    except OSError:
         return None
+    for path in paths:
+        try:
+            kv = {}
+            for line in open(path):
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+            if kv.get("kernel_source_sha256") != sha:
+                continue
+            if int(kv["cells_per_lane"]) != C or int(kv["block_steps"]) != T:
+                continue
+            return float(kv["fetch_bytes_per_update"]) + float(kv["write_bytes_per_update"])
+        except (OSError, KeyError, ValueError):
+            continue
+    return None
 
 
 def measured_traffic_2d(pol, precision, C, xch, T=1):
