@@ -216,11 +216,25 @@ def test_two_stream_batch_equals_alone_bitwise(P):
         b.run()
         got = b.collect()
         st = b.stats()
+        # the tuner times both halves on their streams; the choice changes
+        # only the tiling
+        b.autotune(trial_blocks=2)
+        b.run()
+        tuned = b.collect()
+        st_tuned = b.stats()
     assert st["streams"] == 2 and st["graph"] == 0, st
-    for p, g in zip(probs, got):
+    assert st_tuned["streams"] == 2, st_tuned
+    # a captured pass keeps every launch on one stream
+    with P.Batch(probs, use_graph=1) as b:
+        b.run()
+        graphed = b.collect()
+        st_graph = b.stats()
+    assert st_graph["graph"] == 1 and st_graph["streams"] == 1, st_graph
+    for i, p in enumerate(probs):
         alone = P.gfdtd_solve(p)
         for k in ("trace", "dft", "d", "b"):
-            assert np.array_equal(g[k], alone[k]), (p.label, k)
+            for name, res in (("split", got), ("tuned", tuned), ("graph", graphed)):
+                assert np.array_equal(res[i][k], alone[k]), (p.label, name, k)
 
 
 def test_zero_steps_and_no_probes(P):
