@@ -462,26 +462,52 @@ def gfdtd_solve_batch(problems: Sequence, steps=None, stream=None,
     return [o.as_dict() for o in outs]
 
 
+def _tmm_stack_dtype():
+    """numpy record type laid out as gfdtd_tmm_stack (pointers as uint64)."""
+    f = gfdtd_tmm_stack
+    names = ["struct_size", "nlayers", "beta", "eps", "mu", "widths"]
+    formats = [np.uint32, np.int32, np.float64, np.uint64, np.uint64, np.uint64]
+    return np.dtype({"names": names, "formats": formats,
+                     "offsets": [getattr(f, k).offset for k in names],
+                     "itemsize": C.sizeof(f)})
+
+
 def _tmm_structs(stacks):
-    keep = []
-    arr = (gfdtd_tmm_stack * max(1, len(stacks)))()
-    for i, st in enumerate(stacks):
-        eps = np.ascontiguousarray(st.eps, dtype=np.float64)
-        mu = None if st.mu is None else np.ascontiguousarray(st.mu, dtype=np.float64)
-        widths = np.ascontiguousarray(st.widths, dtype=np.float64)
-        if mu is not None and mu.shape != eps.shape:
+    """The gfdtd_tmm_stack array of `stacks`, filled column-wise: every
+    stack's layers are packed into flat arrays (kept alive by the returned
+    list) and the records point into them."""
+    n = len(stacks)
+    eps = [np.ascontiguousarray(st.eps, dtype=np.float64).ravel() for st in stacks]
+    widths = [np.ascontiguousarray(st.widths, dtype=np.float64).ravel() for st in stacks]
+    mus = [None if st.mu is None else np.ascontiguousarray(st.mu, dtype=np.float64).ravel()
+           for st in stacks]
+    nl = np.array([len(e) for e in eps], dtype=np.int64)
+    nw = np.array([len(w) for w in widths], dtype=np.int64)
+    if np.any(nw != np.maximum(nl - 2, 0)):
+        raise ValueError("widths must hold the inner layers' widths")
+    for e, m in zip(eps, mus):
+        if m is not None and m.shape != e.shape:
             raise ValueError("mu must have one value per layer")
-        if widths.shape != (max(len(eps) - 2, 0),):
-            raise ValueError("widths must hold the inner layers' widths")
-        keep += [eps, mu, widths]
-        a = arr[i]
-        a.struct_size = C.sizeof(gfdtd_tmm_stack)
-        a.nlayers = len(eps)
-        a.beta = float(st.beta)
-        a.eps = eps.ctypes.data_as(_PD)
-        a.mu = mu.ctypes.data_as(_PD) if mu is not None else None
-        a.widths = widths.ctypes.data_as(_PD) if len(widths) else None
-    return arr, keep
+    eps_flat = np.concatenate(eps) if n else np.zeros(1)
+    w_flat = np.concatenate(widths) if n and nw.sum() else np.zeros(1)
+    rec = np.zeros(max(1, n), dtype=_tmm_stack_dtype())
+    keep = [eps_flat, w_flat, rec]
+    if n:
+        rec["struct_size"][:] = C.sizeof(gfdtd_tmm_stack)
+        rec["nlayers"][:] = nl
+        rec["beta"][:] = [float(st.beta) for st in stacks]
+        start = np.concatenate(([0], np.cumsum(nl)[:-1]))
+        rec["eps"][:] = eps_flat.ctypes.data + 8 * start.astype(np.uint64)
+        wstart = np.concatenate(([0], np.cumsum(nw)[:-1]))
+        rec["widths"][:] = np.where(nw > 0, w_flat.ctypes.data + 8 * wstart.astype(np.uint64),
+                                    np.uint64(0))
+        given = [i for i, m in enumerate(mus) if m is not None]
+        if given:
+            mu_flat = np.concatenate([mus[i] for i in given])
+            keep.append(mu_flat)
+            mstart = np.concatenate(([0], np.cumsum([len(mus[i]) for i in given])[:-1]))
+            rec["mu"][given] = mu_flat.ctypes.data + 8 * mstart.astype(np.uint64)
+    return rec.ctypes.data_as(C.POINTER(gfdtd_tmm_stack)), keep
 
 
 def gfdtd_tmm(stacks: Sequence, omegas, stream=None):
@@ -494,13 +520,18 @@ def gfdtd_tmm(stacks: Sequence, omegas, stream=None):
     n = C.c_size_t(0)
     _check(lib.gfdtd_tmm_workspace_bytes(arr, len(stacks), len(om), C.byref(n)))
     ws = _device_buffer(n.value)
-    t = np.zeros((len(stacks), len(om), 2))
-    g = np.zeros((len(stacks), len(om), 2))
+    # (re, im) pairs written by the library are complex128 in memory order;
+    # pinned (page-locked) host buffers let its device-to-host copy run at
+    # full speed (torch caches them between calls)
+    import torch
+    shape = (len(stacks), len(om), 2)
+    t = torch.empty(shape, dtype=torch.float64, pin_memory=True).numpy()
+    g = torch.empty(shape, dtype=torch.float64, pin_memory=True).numpy()
     _check(lib.gfdtd_tmm(arr, len(stacks), om.ctypes.data_as(_PD), len(om),
                          C.c_void_p(ws.data_ptr()), n.value, _stream_handle(stream),
                          t.ctypes.data_as(_PD), g.ctypes.data_as(_PD)))
     del keep
-    return t[..., 0] + 1j * t[..., 1], g[..., 0] + 1j * g[..., 1]
+    return t.view(np.complex128)[..., 0], g.view(np.complex128)[..., 0]
 
 
 def gfdtd_tmm_kernel_ms() -> float:
