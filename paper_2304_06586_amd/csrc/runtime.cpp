@@ -372,6 +372,7 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 // 2.14e12 -> 2.22e12; four parts were slower than two.  Groups under
 // kPartCells cells stay whole.
 constexpr int kParts = 2;
+static_assert(kParts == 2, "parts above 0 share the one second stream");
 constexpr int64_t kPartCells = (int64_t)4 << 20;
 
 template <typename StepsOf>
