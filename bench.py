@@ -87,6 +87,8 @@ KERNEL2D_SRC = os.path.join(ROOT, "paper_2304_06586_amd", "csrc", "kernels2d.hip
 COUNTERS_2D = {
     (W.TE, W.F32): os.path.join(ROOT, "profiles", "k_step2d_f32_te_slab4096_hbm_counters.txt"),
     (W.TE, W.F64): os.path.join(ROOT, "profiles", "k_step2d_f64_te_slab4096_hbm_counters.txt"),
+    (W.TM, W.F32): os.path.join(ROOT, "profiles", "k_step2d_f32_tm_slab4096_hbm_counters.txt"),
+    (W.TM, W.F64): os.path.join(ROOT, "profiles", "k_step2d_f64_tm_slab4096_hbm_counters.txt"),
 }
 # Algorithmic HBM bytes of one 2D cell-update: read and write D, B and C once.
 BYTES_PER_UPDATE_2D = {W.F32: 24, W.F64: 48}
