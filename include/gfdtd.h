@@ -208,7 +208,9 @@ gfdtd_status gfdtd_batch_workspace_bytes(const gfdtd_problem *probs,
  * Execution options (NULL = automatic).  cells_per_lane in {4, 8, 12, 16}
  * (0 = auto), block_steps = temporal block depth, steps per launch
  * (0 = auto; 1 for GFDTD_VARIANT_STEP), use_graph: -1 auto, 0 plain
- * launches, 1 capture the launch sequence in a hipGraph.
+ * launches, 1 capture the launch sequence in a hipGraph (a captured pass
+ * runs every launch on one stream, so use_graph = 1 also keeps groups
+ * whole; automatic never captures a group split over two streams).
  * tile_waves in 0..4 (0 = auto): waves that step one tile side by side,
  * sharing overlap cells through LDS (rings always use 1);
  * exchange_steps in 0..16 (0 = auto, 8): steps between the overlap
@@ -300,10 +302,11 @@ typedef struct gfdtd_stats {
     int32_t tile_waves;          /* waves per tile                         */
     int32_t exchange_steps;      /* steps between overlap refreshes        */
     int32_t streams;             /* streams the stepping launches use: 2
-                                    when a group of at least 4M cells is
-                                    split into two halves whose launches
-                                    overlap (launches and tiles count both),
-                                    else 1                                 */
+                                    when a group of two or more runs and
+                                    at least 2^18 cells is split into two
+                                    halves whose launches overlap
+                                    (launches and tiles count both; not
+                                    with use_graph = 1), else 1            */
     int32_t reserved;
 } gfdtd_stats;
 

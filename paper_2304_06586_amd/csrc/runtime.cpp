@@ -369,11 +369,14 @@ int64_t max_tiles_of(int64_t nz) { return nz / 4 + 1; }
 // keep long runs to the end), each with its own tables, whose launches are
 // issued to two streams: one half's waves fill the other's drain.  Measured
 // on 4096 crystal runs: FP32 3.42e12 -> 3.71e12 cell-updates/s, FP64
-// 2.14e12 -> 2.22e12; four parts were slower than two.  Groups under
-// kPartCells cells stay whole.
+// 2.14e12 -> 2.22e12; four parts were slower than two.  Smaller batches
+// gain more (their launches are shorter, so the drain is a larger share):
+// 128 runs of 2.7 M cells in all, 9600 steps, FP32 1.71e12 -> 2.37e12, and
+// 16 runs of 0.31 M cells 5.2e11 -> 5.4e11.  Groups under kPartCells cells
+// stay whole.
 constexpr int kParts = 2;
 static_assert(kParts == 2, "parts above 0 share the one second stream");
-constexpr int64_t kPartCells = (int64_t)4 << 20;
+constexpr int64_t kPartCells = (int64_t)1 << 18;
 
 template <typename StepsOf>
 std::vector<std::vector<int>> stream_parts(std::vector<int> members, int64_t cells,
@@ -390,22 +393,22 @@ std::vector<std::vector<int>> stream_parts(std::vector<int> members, int64_t cel
 
 // --------------------------------------------------------------- tiling
 
-// Tiling defaults from measurements on MI355X (full-occupancy launches of
-// the 4096-run crystal batch, the autotuner's choice there): FP32 16 cells
-// per lane and 48 steps per launch, FP64 12 and 48 (FP64 holds twice the
-// registers per cell); 4 cells per lane and 24 steps when the group holds
-// few cells (more, narrower tiles keep more SIMDs busy).
+// Tiling defaults from measurements on MI355X, crystal runs split over two
+// streams (cell-updates/s, every run live unless stated):
+// - from 8 M cells, 16 cells per lane and 48 steps per launch (FP32
+//   3.43-3.63e12 from 11 M cells up; on the full 4096-run pass FP64 ran 2 %
+//   faster at 16 than at 12 cells per lane, 2.32e12 against 2.28e12);
+// - from 4 M to 8 M cells, 8 and 48 (5.3 M cells: FP32 2.77e12 against
+//   2.26e12 at 16 cells per lane, FP64 2.22e12 against 1.86e12);
+// - below 4 M cells, 4 and 24: more, narrower tiles keep more SIMDs busy.
 void choose_tiling(int precision, const gfdtd_exec *ex, int64_t max_steps,
                    int64_t total_cells, bool ring, int &C, int &T, int &G, int &K)
 {
     const int variant = ex ? ex->variant : GFDTD_VARIANT_AUTO;
-    // large groups run on two streams, where the wider FP64 tiles win: the
-    // full 4096-run crystal pass at C = 16 ran 2 % faster than at C = 12
-    // (2.32e12 against 2.28e12, three passes each), although with every run
-    // live on one stream C = 12 was 5 % faster
     (void)precision;
     const bool small = total_cells < (int64_t)4 << 20;
-    C = (ex && ex->cells_per_lane) ? ex->cells_per_lane : (small ? 4 : 16);
+    const bool mid = !small && total_cells < (int64_t)8 << 20;
+    C = (ex && ex->cells_per_lane) ? ex->cells_per_lane : (small ? 4 : mid ? 8 : 16);
     if (variant == GFDTD_VARIANT_STEP)
         T = 1;
     else if (ex && ex->block_steps > 0)
@@ -546,6 +549,7 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
             return fail(st, "run %d: %s", i, last_error());
         runs[i] = make_run_host(probs[i], steps_in[i]);
     }
+    use_graph = ex ? ex->use_graph : -1;
     // groups by (precision, kind, ring)
     Carver cv;
     for (auto &r : runs)
@@ -568,8 +572,10 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         choose_tiling(G.precision, ex, max_steps, cells, G.ring, G.C, G.T, G.Gw, G.K);
         for (int i : G.members)
             runs[i].T = G.T;
-        // the allocation-free entry point has no second stream
-        auto parts = stream_parts(G.members, cells, !no_alloc,
+        // the allocation-free entry point has no second stream, and a
+        // captured pass puts every launch on one stream, where two halves
+        // would only double the launches
+        auto parts = stream_parts(G.members, cells, !no_alloc && use_graph != 1,
                                   [&](int i) { return runs[i].steps; });
         for (size_t q = 0; q < parts.size(); ++q) {
             Group H = G;
@@ -586,7 +592,6 @@ gfdtd_status Batch::prepare(const gfdtd_problem *probs, const int64_t *steps_in,
         return fail(GFDTD_E_NOMEM, "workspace %zu bytes < %zu needed", ws_bytes, cv.off);
     if (count > 0 && !ws)
         return fail(GFDTD_E_INVALID, "workspace pointer is NULL");
-    use_graph = ex ? ex->use_graph : -1;
 
     hipError_t e;
     // uploads
@@ -1071,7 +1076,11 @@ int Batch::live_tiles(const Group &G, int64_t b) const
 bool Batch::auto_graph() const
 {
     // plain launches cost a few microseconds each; a graph pays off when
-    // launches are many and each is short
+    // launches are many and each is short.  Not for a batch split over two
+    // streams: a captured pass would run both halves on one stream
+    for (auto &G : groups)
+        if (G.part > 0)
+            return false;
     double updates_per_launch = launches ? cell_updates / (double)launches : 0.0;
     return launches >= 64 && updates_per_launch < 2e7;
 }
