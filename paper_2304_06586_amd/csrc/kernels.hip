@@ -1123,20 +1123,25 @@ __device__ __forceinline__ void tile_body(const RunDesc *__restrict__ rd,
 }
 
 // Occupancy target: waves per SIMD the register allocation must allow
-// (512 registers per SIMD lane, at most 8 waves).  Each value is what the
-// tiling fits in without spilling; stated because the compiler, left to
-// itself, may give up a wave for one or two registers of the full-step loop
-// (FP64 at 12 cells per lane took 169 registers, 2 waves, instead of 168, 3).
+// (512 registers per SIMD lane, at most 8 waves).  Stated because the
+// compiler, left to itself, may give up a wave for one or two registers of
+// the full-step loop (FP64 at 12 cells per lane took 169 registers, 2 waves,
+// instead of 168, 3).  Some targets leave a few bytes of spill in the
+// full-step (edge) code, kept where measured faster than one wave less:
+// FP64 modulation at 12 cells per lane, 3 waves with 28 bytes a lane, ran
+// the crystal batch at 2.30e12 against 2.22e12 with 2 waves and none.  FP32
+// at 8 and FP64 at 4 cells per lane take 6 waves without spill (the FP64
+// slab 1.32e11 against 1.29e11 with 7 waves and 28 bytes).
 template <typename R, int C, int KIND, bool MW>
 constexpr int occupancy_target()
 {
     if constexpr (sizeof(R) == 4) {
         if constexpr (KIND == GFDTD_MODULATION)
-            return C == 4 ? 8 : C == 8 ? 7 : C == 12 ? 5 : 4;
+            return C == 4 ? 8 : C == 8 ? 6 : C == 12 ? 5 : 4;
         return C == 4 ? 8 : C == 8 ? 5 : C == 12 ? 4 : 3;
     } else {
         if constexpr (KIND == GFDTD_MODULATION)
-            return C == 4 ? (MW ? 5 : 7) : C == 8 ? 4 : C == 12 ? 3 : 2;
+            return C == 4 ? (MW ? 5 : 6) : C == 8 ? 4 : C == 12 ? 3 : 2;
         return C == 4 ? 5 : C == 8 ? 3 : C == 12 ? 2 : 1;
     }
 }
