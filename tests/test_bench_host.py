@@ -40,6 +40,44 @@ def test_traffic_counters_only_for_their_kernel_and_tiling(tmp_path, monkeypatch
     assert bench.measured_traffic_per_update(16, 48) is None
 
 
+def test_counters_list_takes_the_matching_tiling(tmp_path, monkeypatch):
+    """A precision may have counters at several tilings; the lookup takes
+    the file taken at the run's tiling."""
+    import hashlib
+    import workloads as W
+    sha = hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()
+    files = []
+    for C, f in ((16, 1.0), (12, 2.0)):
+        prof = tmp_path / f"c{C}.txt"
+        prof.write_text(f"kernel_source_sha256: {sha}\ncells_per_lane: {C}\nblock_steps: 48\n"
+                        f"fetch_bytes_per_update: {f}\nwrite_bytes_per_update: 0.5\n")
+        files.append(str(prof))
+    monkeypatch.setitem(bench.COUNTERS, W.F64, files)
+    assert bench.measured_traffic_per_update(16, 48, W.F64) == 1.5
+    assert bench.measured_traffic_per_update(12, 48, W.F64) == 2.5
+    assert bench.measured_traffic_per_update(8, 48, W.F64) is None
+
+
+def test_roofline_of_launches_on_two_streams(monkeypatch):
+    """With the runs split over two streams, each stream is busy for the
+    whole stepping phase: a launch lasts 2 x step time / launches, and the
+    achieved rate is the flops of all launches over the phase."""
+    import workloads as W
+    monkeypatch.setattr(bench, "measured_traffic_per_update", lambda C, T, p=W.F32: 0.5)
+    st = {"step_ms": 1000.0, "launches": 400, "streams": 2, "cells_per_lane": 16,
+          "block_steps": 48, "tile_waves": 1, "graph": 0}
+    updates = 2.0e12
+    r = bench.kernel_roofline(st, updates, W.F32)
+    assert r["concurrent_streams"] == 2
+    assert abs(r["avg_launch_ms"] - 5.0) < 1e-12
+    assert abs(r["achieved"] - updates * bench.FLOPS_PER_UPDATE / 1e12) < 1e-3
+    # traffic per launch at 0.5 B an update, both streams' launches over 1 s
+    assert abs(r["traffic"] - 0.5 * updates / 400) < 1e-6
+    assert abs(r["measured_hbm_GBs"] - 0.5 * updates / 1e9) < 0.1
+    one = bench.kernel_roofline(dict(st, streams=1), updates, W.F32)
+    assert abs(one["avg_launch_ms"] - 2.5) < 1e-12 and one["achieved"] == r["achieved"]
+
+
 class _FakeServer:
     """One request in service at a time, each needing `work` progress
     calls; the rest wait in the queue."""
