@@ -272,7 +272,10 @@ typedef struct gfdtd_batch gfdtd_batch;
 /*
  * Validate and pre-flight every problem, carve the workspace, upload rest
  * profiles, probes and frequencies, and build the launch plan (and the
- * hipGraph if requested).  Enqueues uploads on `stream`.
+ * hipGraph if requested).  Enqueues uploads on `stream`.  A group of two or
+ * more runs and at least 2^18 cells (not with use_graph = 1) is split into
+ * two halves; the batch then creates a second, non-blocking stream of
+ * default priority, owned by it and destroyed with it.
  */
 gfdtd_status gfdtd_batch_prepare(const gfdtd_problem *probs,
                                  const int64_t *steps, int32_t count,
@@ -283,6 +286,11 @@ gfdtd_status gfdtd_batch_prepare(const gfdtd_problem *probs,
  * Enqueue one complete pass on the stream: zero the fields, time-step
  * every run to its step count, then form the probe DFTs.  Device work
  * only; returns without waiting.  Each pass recomputes from zero fields.
+ * With a split group, the second half's stepping launches run on the
+ * batch's second stream, which waits (by an event) for the work already
+ * enqueued on `stream` and which `stream` waits for before the DFTs: work
+ * the caller enqueues on `stream` afterwards is ordered after the whole
+ * pass, as without the split.
  */
 gfdtd_status gfdtd_batch_run(gfdtd_batch *b);
 /* Wait for the stream, then copy run i's results to outs[i]. */
