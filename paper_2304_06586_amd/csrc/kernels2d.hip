@@ -733,17 +733,18 @@ Launch2D plan_launch2d(int64_t nx, int64_t nz, int precision, int C, int xch, in
     L.nstrips = (nz + strip_rows(C, T) - 1) / strip_rows(C, T);
     if (xch <= 0) {
         // a march of T steps starts T + 1 columns early, so deeper blocks
-        // want longer marches: at most 8, 16, 16 and 16 (FP32) or 24 (FP64)
+        // want longer marches: at most 8, 16, 16 and 16 (FP32) or 20 (FP64)
         // columns for T = 1..4, fewer when the grid would give under 2048
         // waves.  Measured on the 4096 x 4096 grid at 2 cells per lane and
         // 4 steps a launch: FP32 3.6e11 updates/s with 16 columns against
-        // 3.0e11 with 32 (TE; TM 3.3e11 against 3.1e11), FP64 flat from 20
-        // to 32; one step a launch with 8-16
+        // 3.0e11 with 32 (TE; TM 3.3e11 against 3.1e11); FP64 TE flat from
+        // 20 to 32, TM 2.41e11 with 20 against 2.33e11 with 24; one step a
+        // launch with 8-16
         static const int cap_of[5] = {8, 8, 16, 16, 16};
         const int64_t x = nx * L.nstrips / 2048;
         int64_t cap = cap_of[T < 0 ? 0 : (T > 4 ? 4 : T)];
         if (T >= 4 && precision != GFDTD_F32)
-            cap = 24;
+            cap = 20;
         xch = (int)(x < 2 ? 2 : (x > cap ? cap : x));
     }
     if (xch > nx)
